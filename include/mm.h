@@ -1,0 +1,196 @@
+/*
+ * mm.h -- C ABI of the MI355X map-making library (block-Jacobi PCG for the maximum-likelihood
+ * map-making system of arXiv:2112.03370).
+ *
+ * The library solves, on one GPU,
+ *
+ *     (P^T N^-1 P) m = P^T N^-1 d                      (Eq. genMapEstimator with F_T = N^-1)
+ *
+ * where P is the pointing matrix with three non-zeros per row, (1, cos 2psi, sin 2psi), in the
+ * columns of the pixel observed by the sample (Eq. dataModelSingleSlot, Eq. dataModelHwp), and
+ * N^-1 is block-diagonal with one symmetric banded Toeplitz block per stationary interval
+ * (Eq. MADCAP; the stbmm product of the Toeplitz algebra package: samples outside every block
+ * are passed through unchanged).  The solver is PCG (Alg. 1) with the block-Jacobi
+ * preconditioner M_BD = (P^T diag(N^-1) P)^-1 (BJ paragraph of the preconditioner section).
+ *
+ * Conventions
+ *   - Every function returns an mm_status; none aborts, throws or exits.  On error the
+ *     thread-local detail string is available from mm_last_error().
+ *   - "DEVICE" pointers are HIP device (HBM) addresses owned by the caller; "HOST" pointers are
+ *     ordinary host memory owned by the caller.  The library never frees caller memory.
+ *   - Pixel-domain vectors are FP64, pixel-major: [k][n_kept][3] (I, Q, U), where n_kept is
+ *     the number of kept pixels of the plan, ordered by ascending global pixel id.
+ *   - Time-domain vectors are FP32 with n_samples entries per right-hand side, detector-major.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Asynchronous calls
+ *     are ordered on that stream; calls on one plan must not overlap (they share its workspace).
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mm_status;
+
+enum {
+  MM_OK = 0,
+  MM_PENDING = 1,            /* mm_poll: request not finished yet */
+  MM_ERR_INVALID = -1,       /* bad argument, index out of range, overlapping blocks, ... */
+  MM_ERR_NOT_SPD = -2,       /* band symbol <= 0, or p^T A p <= 0 / r^T z <= 0 in PCG */
+  MM_ERR_NO_CONV = -3,       /* max_iter reached; the last iterate is returned */
+  MM_ERR_OOM = -4,           /* device allocation failed */
+  MM_ERR_HIP = -5,           /* a HIP runtime call failed */
+  MM_ERR_BUDGET = -6,        /* serving: request can never fit the memory budget */
+  MM_ERR_UNSUPPORTED = -7,   /* valid input outside what this build implements */
+  MM_ERR_NOT_FOUND = -8      /* serving: unknown ticket */
+};
+
+enum { MM_TOEPLITZ_AUTO = 0, MM_TOEPLITZ_DIRECT = 1, MM_TOEPLITZ_FFT = 2 };
+
+typedef struct mm_plan mm_plan_t;
+typedef struct mm_server mm_server_t;
+
+/*
+ * Problem geometry (pointing + block-Toeplitz inverse noise).
+ *   pix[s]      DEVICE int32 [n_samples]  global pixel id in [0, n_pix_global), -1 = flagged.
+ *   w_q, w_u    DEVICE float [n_samples]  cos 2psi_s, sin 2psi_s (the I weight is 1).
+ *   blk_*       HOST [n_blocks]            stationary intervals: first sample, length >= 1,
+ *                                          band index.  Blocks must not overlap and, when
+ *                                          det_offset is given, must not cross detectors.
+ *   band_*      HOST [n_bands]             band b holds band_ncoef[b] = lambda_b + 1 FP32
+ *                                          coefficients c_0..c_lambda at band_coef +
+ *                                          band_offset[b] (first row of the Toeplitz block).
+ *   det_offset  HOST [n_dets + 1] or NULL  first sample of each detector (validation only).
+ *   cond_max    excision threshold on the 2-norm condition number of each pixel's 3x3 BJ
+ *               block; <= 0 selects 1e3.  Pixels with fewer than 3 hits are excised too.
+ *   toeplitz_algo  MM_TOEPLITZ_*; fft_size  real FFT length for the overlap-save product
+ *               (power of two in [2^11, 2^15], > 2 lambda_max), 0 = automatic.
+ * All pointers are read only during mm_plan and may be released afterwards.
+ */
+typedef struct {
+  int64_t n_samples;
+  const int32_t* pix;
+  const float* w_q;
+  const float* w_u;
+  int64_t n_pix_global;
+  int32_t n_blocks;
+  const int64_t* blk_start;
+  const int64_t* blk_len;
+  const int32_t* blk_band;
+  int32_t n_bands;
+  const int32_t* band_ncoef;
+  const int64_t* band_offset;
+  const float* band_coef;
+  int32_t n_dets;
+  const int64_t* det_offset;
+  double cond_max;
+  int32_t toeplitz_algo;
+  int32_t fft_size;
+} mm_geometry;
+
+typedef struct {
+  int64_t n_samples;
+  int64_t n_pix_global;
+  int64_t n_obs;          /* pixels with at least one unflagged sample */
+  int64_t n_kept;         /* pixels solved for */
+  int64_t n_excised;      /* n_obs - n_kept */
+  int64_t n_gap_samples;  /* flagged or excised samples (zero rows of P) */
+  int64_t device_bytes;   /* device memory owned by the plan */
+  int32_t lambda_max;
+  int32_t toeplitz_algo;  /* algorithm actually used */
+  int32_t fft_size;       /* 0 when not using the FFT product */
+  int32_t n_blocks;
+  int32_t n_chunks;       /* overlap-save segments (FFT) or tiles (direct) per product */
+} mm_plan_info_t;
+
+typedef struct {
+  double tol;             /* stop when ||r_k||_2 < tol ||b||_2 (Alg. 1); <= 0 selects 1e-8 */
+  int32_t max_iter;       /* <= 0 selects 10000 */
+  int32_t use_x0;         /* nonzero: start from the x passed in (restart); else x0 = 0 */
+  int32_t check_every;    /* iterations between host convergence checks; <= 0 automatic */
+  int32_t use_graph;      /* nonzero: replay iterations from a captured HIP graph */
+} mm_solve_opts;
+
+typedef struct {
+  int32_t iterations;     /* PCG iterations (A products inside the loop) */
+  int32_t converged;      /* 1 when the stopping test passed */
+  double relres;          /* recursive ||r_k|| / ||b|| */
+  double true_relres;     /* ||b - A x_k|| / ||b|| with one more product, FP64 reductions */
+  double bnorm;           /* ||b||_2 */
+  double ms;              /* wall time of the solve on the stream (hipEvent) */
+} mm_solve_info;
+
+/* mm_plan -- build the device plan: copy the pointing to the device plan, count hits, build
+ * the 3x3 BJ blocks sum_s diag(N^-1)_s w_s w_s^T (diag(N^-1) = c_0 of the sample's band, 1
+ * outside blocks), excise pixels with < 3 hits or condition number > cond_max together with
+ * their samples (Degeneracy section), compact global -> local pixels (MAPMAT local indexing),
+ * invert the kept blocks, and check that every band's symbol c_0 + 2 sum_k c_k cos(k w) is
+ * positive (so every Toeplitz block and A are SPD).  Synchronous on `stream`.  The plan owns
+ * all its device memory and is immutable.
+ * Errors: MM_ERR_INVALID (bad sizes, pixel id out of range, overlapping blocks), MM_ERR_NOT_SPD
+ * (non-positive symbol), MM_ERR_UNSUPPORTED (lambda beyond the implemented products),
+ * MM_ERR_OOM, MM_ERR_HIP.  *out is NULL on error. */
+mm_status mm_plan(const mm_geometry* g, void* stream, mm_plan_t** out);
+
+/* Release a plan (NULL allowed).  The caller must have synchronised its streams. */
+mm_status mm_plan_destroy(mm_plan_t* plan);
+
+/* Plan statistics (host struct). */
+mm_status mm_plan_info(const mm_plan_t* plan, mm_plan_info_t* out);
+
+/* Kept pixels: HOST outputs with n_kept entries each (either may be NULL): ascending global
+ * ids and their hit counts (unflagged samples).  Bit-exact integers.  Synchronous. */
+mm_status mm_plan_pixels(const mm_plan_t* plan, int64_t* global_ids, int32_t* hits);
+
+/* t = P x (un-pointing, MAPMAT).  x DEVICE double [n_kept][3]; t DEVICE float [n_samples];
+ * gap samples get 0.  Sums in FP64, stored FP32.  Asynchronous. */
+mm_status mm_unpoint(const mm_plan_t* plan, const double* x, float* t, void* stream);
+
+/* u = N^-1 t (block-diagonal banded Toeplitz; identity outside blocks; truncated at block
+ * edges).  t, u DEVICE float [n_samples], must not alias.  FP32.  Asynchronous. */
+mm_status mm_noise_weight(const mm_plan_t* plan, const float* t, float* u, void* stream);
+
+/* y = P^T u (pointing, MAPMAT): y[p] = sum over samples of p of (1, cos, sin) u_s, FP64
+ * accumulation.  y DEVICE double [n_kept][3] is overwritten.  Asynchronous. */
+mm_status mm_point(const mm_plan_t* plan, const float* u, double* y, void* stream);
+
+/* b = P^T N^-1 d for k right-hand sides; d DEVICE float, column j at d + j*ld_d (ld_d >=
+ * n_samples); gap samples of d are ignored.  b DEVICE double [k][n_kept][3].  Asynchronous. */
+mm_status mm_rhs(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d, double* b,
+                 void* stream);
+
+/* y = P^T N^-1 P x (the system product, applied right to left), k columns.  x, y DEVICE
+ * double [k][n_kept][3], must not alias.  Asynchronous. */
+mm_status mm_apply_A(const mm_plan_t* plan, const double* x, double* y, int32_t k,
+                     void* stream);
+
+/* z = M_BD r, per pixel 3x3 FP64.  r, z DEVICE double [k][n_kept][3] (may alias).  Async. */
+mm_status mm_precond_bj(const mm_plan_t* plan, const double* r, double* z, int32_t k,
+                        void* stream);
+
+/* Solve A x = P^T N^-1 d by PCG (Alg. 1) for k right-hand sides (each column independently).
+ * d as in mm_rhs; x DEVICE double [k][n_kept][3] (read when opts->use_x0); info HOST array of
+ * k entries (may be NULL).  opts may be NULL (defaults).  Synchronous: returns when x holds
+ * the maps.  Errors: MM_ERR_NO_CONV (x = last iterate), MM_ERR_NOT_SPD, MM_ERR_HIP. */
+mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d,
+                       double* x, const mm_solve_opts* opts, mm_solve_info* info,
+                       void* stream);
+
+/* Per-kernel timing (HIP events recorded on the launch stream around every launch of the
+ * plan's kernels while enabled; graphs are not used then).  kind: 0 un-pointing, 1 Toeplitz
+ * product, 2 pointing (P^T), 3 CG vector kernels.  Outputs total milliseconds and launch count
+ * since the last reset.  Synchronous. */
+mm_status mm_set_timing(mm_plan_t* plan, int32_t enable);
+mm_status mm_kernel_time(mm_plan_t* plan, int32_t kind, double* total_ms, int64_t* launches);
+
+const char* mm_status_string(mm_status s);
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

@@ -1,0 +1,393 @@
+// Preconditioned conjugate gradient (Alg. 1) on the device.
+//
+// Per iteration: q = A p (un-pointing, Toeplitz product, pointing), then three pixel-domain
+// kernels and two one-workgroup scalar kernels:
+//   k_dot_pq     partial sums of <p, q>
+//   k_alpha      alpha = <r, z> / <p, q> (breakdown flag when <p, q> <= 0)
+//   k_update     x += alpha p, r -= alpha q, z = M_BD r, q = 0; partials of ||r||^2, <r, z>
+//   k_beta       stop test ||r|| < eps ||b||, beta = <r', z'> / <r, z>, iteration count
+//   k_direction  p = z + beta p
+// All scalars live in a device CgState and all reductions are FP64 with a fixed summation
+// order (deterministic).  Every kernel returns at once when the state's `done` flag is set,
+// so iterations can be queued (or replayed from a captured graph) in chunks and the host only
+// reads the state between chunks.  Zeroing is done by kernels (no memset nodes in graphs).
+#include <chrono>
+#include <cmath>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPerBlock = 1024;  // elements per workgroup per grid-stride step
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kThreads / 64; ++i) s += sh[i];
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+// Sum of partials[0..n) by one workgroup in a fixed order.
+__device__ __forceinline__ double reduce_partials(const double* p, int n, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) v += p[i];
+  return block_sum(v, sh);
+}
+
+// z = M_BD r for pixel i of a [*, n_kept, 3] layout (minv shared across columns).
+__device__ __forceinline__ void bj_apply(const double* __restrict__ m6, const double* r,
+                                         double* z) {
+  const double r0 = r[0], r1 = r[1], r2 = r[2];
+  z[0] = m6[0] * r0 + m6[1] * r1 + m6[2] * r2;
+  z[1] = m6[1] * r0 + m6[3] * r1 + m6[4] * r2;
+  z[2] = m6[2] * r0 + m6[4] * r1 + m6[5] * r2;
+}
+
+__global__ __launch_bounds__(kThreads) void k_precond(const double* __restrict__ minv,
+                                                      const double* r, double* z, int64_t n_kept,
+                                                      int64_t n_pix_total) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n_pix_total;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double* m6 = minv + 6 * (i % n_kept);
+    double zz[3];
+    bj_apply(m6, r + 3 * i, zz);
+    z[3 * i] = zz[0];
+    z[3 * i + 1] = zz[1];
+    z[3 * i + 2] = zz[2];
+  }
+}
+
+// r = b - Ax (use_x0) or r = b; z = M r; p = z; q = 0; partials: [0] b.b, [1] r.z, [2] r.r
+__global__ __launch_bounds__(kThreads) void k_init(const double* __restrict__ minv,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ ax, double* r,
+                                                   double* z, double* p, double* q,
+                                                   double* x, int use_x0, int64_t n_kept,
+                                                   double* partial, int nrb) {
+  __shared__ double sh[kThreads / 64];
+  double bb = 0.0, rz = 0.0, rr = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n_kept;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    double rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) {
+      const double bv = b[3 * i + c];
+      bb += bv * bv;
+      rv[c] = use_x0 ? bv - ax[3 * i + c] : bv;
+      rr += rv[c] * rv[c];
+    }
+    bj_apply(minv + 6 * i, rv, zv);
+    for (int c = 0; c < 3; ++c) {
+      r[3 * i + c] = rv[c];
+      z[3 * i + c] = zv[c];
+      p[3 * i + c] = zv[c];
+      q[3 * i + c] = 0.0;
+      if (!use_x0) x[3 * i + c] = 0.0;
+      rz += rv[c] * zv[c];
+    }
+  }
+  const double s0 = block_sum(bb, sh);
+  const double s1 = block_sum(rz, sh);
+  const double s2 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[nrb + blockIdx.x] = s1;
+    partial[2 * nrb + blockIdx.x] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_init_state(CgState* st, const double* partial,
+                                                         int nrb, double tol, int max_iter) {
+  __shared__ double sh[kThreads / 64];
+  const double bb = reduce_partials(partial, nrb, sh);
+  const double rz = reduce_partials(partial + nrb, nrb, sh);
+  const double rr = reduce_partials(partial + 2 * nrb, nrb, sh);
+  if (threadIdx.x == 0) {
+    st->bb = bb;
+    st->rz = rz;
+    st->rr = rr;
+    st->tol2bb = tol * tol * bb;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->pq = 0.0;
+    st->iter = 0;
+    st->max_iter = max_iter;
+    if (bb == 0.0 || rr < st->tol2bb) {
+      st->done = 1;
+    } else if (!(rz > 0.0)) {
+      st->done = 2;
+    } else {
+      st->done = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot_pq(const double* __restrict__ p,
+                                                     const double* __restrict__ q, int64_t n,
+                                                     double* partial, const CgState* st) {
+  __shared__ double sh[kThreads / 64];
+  if (st->done) return;
+  double v = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    v += p[i] * q[i];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_alpha(CgState* st, const double* partial, int nrb) {
+  __shared__ double sh[kThreads / 64];
+  if (st->done) return;
+  const double pq = reduce_partials(partial, nrb, sh);
+  if (threadIdx.x == 0) {
+    st->pq = pq;
+    if (!(pq > 0.0)) {
+      st->done = 2;
+    } else {
+      st->alpha = st->rz / pq;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_update(const double* __restrict__ minv, double* x,
+                                                     double* r, double* z,
+                                                     const double* __restrict__ p, double* q,
+                                                     int64_t n_kept, double* partial, int nrb,
+                                                     const CgState* st) {
+  __shared__ double sh[kThreads / 64];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n_kept;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    double rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) {
+      const int64_t j = 3 * i + c;
+      x[j] += alpha * p[j];
+      rv[c] = r[j] - alpha * q[j];
+      q[j] = 0.0;
+      r[j] = rv[c];
+      rr += rv[c] * rv[c];
+    }
+    bj_apply(minv + 6 * i, rv, zv);
+    for (int c = 0; c < 3; ++c) {
+      z[3 * i + c] = zv[c];
+      rz += rv[c] * zv[c];
+    }
+  }
+  const double s0 = block_sum(rr, sh);
+  const double s1 = block_sum(rz, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[nrb + blockIdx.x] = s1;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_beta(CgState* st, const double* partial, int nrb) {
+  __shared__ double sh[kThreads / 64];
+  if (st->done) return;
+  const double rr = reduce_partials(partial, nrb, sh);
+  const double rz = reduce_partials(partial + nrb, nrb, sh);
+  if (threadIdx.x == 0) {
+    st->iter += 1;
+    st->rr = rr;
+    if (rr < st->tol2bb) {
+      st->done = 1;
+    } else if (st->iter >= st->max_iter) {
+      st->done = 3;
+    } else if (!(rz > 0.0)) {
+      st->done = 2;
+    } else {
+      st->beta = rz / st->rz;
+      st->rz = rz;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_direction(const double* __restrict__ z, double* p,
+                                                        int64_t n, const CgState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    p[i] = z[i] + beta * p[i];
+}
+
+// partial = ||b - y||^2 per block
+__global__ __launch_bounds__(kThreads) void k_resid(const double* __restrict__ b,
+                                                    const double* __restrict__ y, int64_t n,
+                                                    double* partial) {
+  __shared__ double sh[kThreads / 64];
+  double v = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double d = b[i] - y[i];
+    v += d * d;
+  }
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_to(double* out, const double* partial,
+                                                        int nrb) {
+  __shared__ double sh[kThreads / 64];
+  const double s = reduce_partials(partial, nrb, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// One PCG iteration (all launches gated by state->done).
+mm_status iteration(Plan* P, double* x, hipStream_t s) {
+  const int32_t* done = &P->state->done;
+  const int nrb = P->n_red_blocks;
+  const int64_t nk = P->n_kept;
+  MM_TRY(launch_unpoint(P, P->p, P->t, done, s));
+  MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
+  MM_TRY(launch_point(P, P->u, P->q, false, done, s));
+  TimedLaunch tl(P, K_CG, s);
+  hipLaunchKernelGGL(k_dot_pq, dim3(nrb), dim3(kThreads), 0, s, P->p, P->q, 3 * nk, P->partial,
+                     P->state);
+  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kThreads), 0, s, P->state, P->partial, nrb);
+  hipLaunchKernelGGL(k_update, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, P->r, P->z, P->p,
+                     P->q, nk, P->partial, nrb, P->state);
+  hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, P->state, P->partial, nrb);
+  hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, P->z, P->p, 3 * nk, P->state);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace
+
+mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s) {
+  // r and z may alias: each element is read (all three components) before written.
+  const int64_t n = P->n_kept;
+  if (n == 0) return MM_OK;
+  int64_t g = (n + kThreads - 1) / kThreads;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_precond, dim3(static_cast<unsigned>(g)), dim3(kThreads), 0, s, P->minv, r,
+                     z, n, n);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s) {
+  MM_TRY(launch_unpoint(P, x, P->t, done, s));
+  MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
+  MM_TRY(launch_point(P, P->u, y, true, done, s));
+  return MM_OK;
+}
+
+mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
+                    mm_solve_info* info, hipStream_t s) {
+  mm_solve_opts opts{};
+  if (o) opts = *o;
+  const double tol = opts.tol > 0 ? opts.tol : 1e-8;
+  const int max_iter = opts.max_iter > 0 ? opts.max_iter : 10000;
+  const int nrb = P->n_red_blocks;
+  const int64_t nk = P->n_kept;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  MM_HIP_TRY(hipEventCreate(&ev0));
+  MM_HIP_TRY(hipEventCreate(&ev1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{ev0, ev1};
+  MM_HIP_TRY(hipEventRecord(ev0, s));
+
+  // b = P^T N^-1 d
+  MM_TRY(launch_mask_data(P, d, P->t, s));
+  MM_TRY(launch_noise_weight(P, P->t, P->u, nullptr, s));
+  MM_TRY(launch_point(P, P->u, P->b, true, nullptr, s));
+  if (opts.use_x0) MM_TRY(apply_A(P, x, P->q, nullptr, s));
+  hipLaunchKernelGGL(k_init, dim3(nrb), dim3(kThreads), 0, s, P->minv, P->b, P->q, P->r, P->z,
+                     P->p, P->q, x, opts.use_x0 ? 1 : 0, nk, P->partial, nrb);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, P->state, P->partial, nrb, tol,
+                     max_iter);
+  MM_HIP_TRY(hipGetLastError());
+
+  // Iterate in chunks; the host reads the state between chunks.
+  int chunk = opts.check_every > 0 ? opts.check_every : 4;
+  const bool use_graph = opts.use_graph && !P->timing.enabled;
+  hipGraphExec_t gexec = nullptr;
+  int graph_chunk = 0;
+  struct GraphGuard {
+    hipGraphExec_t* e;
+    ~GraphGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+    }
+  } gg{&gexec};
+  int queued = 0;
+  while (true) {
+    MM_HIP_TRY(hipMemcpyAsync(P->h_state, P->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    if (P->h_state->done) break;
+    if (queued >= max_iter + 1) break;  // safety: the device stops at max_iter
+    if (use_graph) {
+      if (gexec == nullptr || graph_chunk != chunk) {
+        if (gexec) {
+          MM_HIP_TRY(hipGraphExecDestroy(gexec));
+          gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        MM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        mm_status st = MM_OK;
+        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, x, s);
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (st != MM_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return st;
+        }
+        if (ce != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(MM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        graph_chunk = chunk;
+      }
+      MM_HIP_TRY(hipGraphLaunch(gexec, s));
+    } else {
+      for (int i = 0; i < chunk; ++i) MM_TRY(iteration(P, x, s));
+    }
+    queued += chunk;
+    if (opts.check_every <= 0 && chunk < 64) chunk *= 2;
+  }
+
+  // True residual with one more product.
+  const CgState st = *P->h_state;
+  double true_rr = 0.0;
+  if (nk > 0 && st.bb > 0.0) {
+    MM_TRY(apply_A(P, x, P->q, nullptr, s));
+    hipLaunchKernelGGL(k_resid, dim3(nrb), dim3(kThreads), 0, s, P->b, P->q, 3 * nk, P->partial);
+    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kThreads), 0, s, &P->state->spare, P->partial,
+                       nrb);
+    MM_HIP_TRY(hipGetLastError());
+    MM_HIP_TRY(hipMemcpyAsync(&P->h_state->spare, &P->state->spare, sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+  }
+  MM_HIP_TRY(hipEventRecord(ev1, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  true_rr = P->h_state->spare;
+  float ms = 0.0f;
+  MM_HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+  if (info) {
+    info->iterations = st.iter;
+    info->converged = st.done == 1 ? 1 : 0;
+    info->bnorm = std::sqrt(st.bb);
+    info->relres = st.bb > 0 ? std::sqrt(st.rr / st.bb) : 0.0;
+    info->true_relres = st.bb > 0 ? std::sqrt(true_rr / st.bb) : 0.0;
+    info->ms = ms;
+  }
+  if (st.done == 2) return fail(MM_ERR_NOT_SPD, "PCG breakdown: p^T A p <= 0 or r^T z <= 0");
+  if (st.done != 1) return fail(MM_ERR_NO_CONV, "PCG reached max_iter without converging");
+  return MM_OK;
+}
+
+}  // namespace mm

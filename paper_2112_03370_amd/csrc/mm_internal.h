@@ -1,0 +1,190 @@
+// Internal declarations shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------------
+
+void set_error(const std::string& msg);
+const char* last_error_cstr();
+mm_status fail(mm_status s, const std::string& msg);
+
+#define MM_HIP_TRY(expr)                                                                 \
+  do {                                                                                   \
+    hipError_t e__ = (expr);                                                             \
+    if (e__ != hipSuccess)                                                               \
+      return ::mm::fail(MM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+  } while (0)
+
+#define MM_TRY(expr)                 \
+  do {                               \
+    mm_status s__ = (expr);          \
+    if (s__ != MM_OK) return s__;    \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------------------------
+
+// One overlap-save segment of the FFT Toeplitz product: outputs [out0, out0 + out_len) of the
+// block [blk_start, blk_start + blk_len) with band `band`.
+struct Chunk {
+  int64_t out0;
+  int64_t blk_start;
+  int32_t blk_len;
+  int32_t out_len;
+  int32_t band;
+  int32_t pad;
+};
+
+// Samples [start, start + len) with one diagonal weight c0 (plan-time tiles).
+struct Tile {
+  int64_t start;
+  int32_t len;
+  float c0;
+};
+
+// Device-resident PCG scalars.
+struct CgState {
+  double rz;        // <r, z> of the current iterate
+  double alpha;
+  double beta;
+  double bb;        // ||b||^2
+  double rr;        // ||r||^2 of the latest iterate
+  double tol2bb;    // tol^2 ||b||^2
+  double pq;
+  double spare;
+  int32_t iter;
+  int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 iteration limit
+  int32_t max_iter;
+  int32_t pad;
+};
+
+enum KernelKind { K_UNPOINT = 0, K_TOEPLITZ = 1, K_POINT = 2, K_CG = 3, K_NKINDS = 4 };
+
+struct Timing {
+  bool enabled = false;
+  std::vector<hipEvent_t> pending[K_NKINDS];  // start/stop pairs
+  double total_ms[K_NKINDS] = {0, 0, 0, 0};
+  int64_t count[K_NKINDS] = {0, 0, 0, 0};
+};
+
+struct Plan {
+  int device = 0;
+  int64_t n_samples = 0;
+  int64_t n_pix_global = 0;
+  int64_t n_obs = 0;
+  int64_t n_kept = 0;
+  int64_t n_gap = 0;
+  int32_t lambda_max = 0;
+  int32_t algo = MM_TOEPLITZ_FFT;
+  int32_t fft_n = 0;       // real FFT length
+  int32_t n_blocks = 0;
+  int32_t n_bands = 0;
+  int64_t device_bytes = 0;
+
+  // pointing (device)
+  int32_t* lpix = nullptr;  // local pixel or -1
+  float* wq = nullptr;
+  float* wu = nullptr;
+
+  // pixel domain (device)
+  double* minv = nullptr;   // [n_kept][6]: 00 01 02 11 12 22 of B^-1
+  int32_t* hits = nullptr;  // [n_kept]
+  int64_t* kept_ids = nullptr;
+
+  // Toeplitz (device)
+  float* band_coef = nullptr;   // concatenated c_0..c_lambda
+  int64_t* band_off = nullptr;
+  int32_t* band_ncoef = nullptr;
+  float* spec = nullptr;        // [n_bands][fft_n/2 + 1], scaled for the in-kernel transform
+  float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
+  float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
+  Chunk* chunks = nullptr;      // FFT segments or direct tiles
+  int32_t n_chunks = 0;
+  int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
+  int32_t n_id_seg = 0;
+  std::vector<int64_t> h_id_seg;
+
+  // workspace (device)
+  float* t = nullptr;
+  float* u = nullptr;
+  double* r = nullptr;
+  double* z = nullptr;
+  double* p = nullptr;
+  double* q = nullptr;
+  double* b = nullptr;
+  double* partial = nullptr;    // reduction partials, 4 slots of n_red_blocks
+  int32_t n_red_blocks = 0;
+  CgState* state = nullptr;
+  CgState* h_state = nullptr;   // pinned host mirror
+
+  Timing timing;
+  std::mutex mu;
+};
+
+// Allocation helper tracking plan bytes.
+template <class T>
+mm_status dalloc(Plan* P, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return MM_OK;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(MM_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  P->device_bytes += static_cast<int64_t>(count * sizeof(T));
+  return MM_OK;
+}
+
+// Timing scope: records events around launches of one kernel kind when enabled.
+struct TimedLaunch {
+  Plan* P;
+  int kind;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimedLaunch(Plan* plan, int k, hipStream_t st);
+  ~TimedLaunch();
+};
+
+// ---------------------------------------------------------------------------------------------
+// Kernel launchers (all asynchronous on `s`; `done` may be null, else kernels exit when *done)
+// ---------------------------------------------------------------------------------------------
+
+mm_status launch_unpoint(Plan* P, const double* x, float* t, const int32_t* done, hipStream_t s);
+mm_status launch_mask_data(Plan* P, const float* d, float* t, hipStream_t s);
+mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* done,
+                              hipStream_t s);
+mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, const int32_t* done,
+                       hipStream_t s);
+mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s);
+mm_status launch_zero(double* y, int64_t n, hipStream_t s);
+
+// A x -> y (y overwritten), done-gated.
+mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s);
+
+// Plan construction (plan.hip).
+mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out);
+void destroy_plan(Plan* P);
+
+// PCG (cg.hip).
+mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
+                    mm_solve_info* info, hipStream_t s);
+
+// FFT sizing helpers (toeplitz.hip).
+int32_t choose_fft_size(int32_t lambda_max);
+bool fft_size_supported(int32_t n);
+int32_t max_direct_lambda();
+
+}  // namespace mm

@@ -1,0 +1,633 @@
+// Plan construction: hits, block-Jacobi blocks, excision, compaction, band symbols.
+//
+// Follows the block-Jacobi preconditioner construction (accumulate P^T diag(N^-1) P per pixel,
+// then invert each 3x3 block and evaluate its condition number, excising ill-conditioned
+// pixels and their samples, Degeneracy section) and MAPMAT's global/local pixel indexing (the
+// local index of a kept pixel is the rank of its global id).  All per-sample and per-pixel work
+// runs in the kernels below; the host only validates the small block/band tables, lays out
+// the segment tables and sizes the allocations.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "mm_internal.h"
+#include "wave_runs.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 4096;        // samples per plan tile (never crossing a block edge)
+constexpr int kScanChunk = 4096;   // pixels per compaction workgroup
+
+// ---- hits + BJ blocks over global pixels ---------------------------------------------------
+
+struct BjFlush {
+  double* B;        // [n_pix_global][6]
+  int32_t* hits;    // [n_pix_global]
+  __device__ void operator()(int key, const double (&v)[7]) const {
+    double* dst = B + 6 * static_cast<int64_t>(key);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) unsafeAtomicAdd(dst + c, v[c]);
+    atomicAdd(hits + key, static_cast<int32_t>(v[6] + 0.5));
+  }
+};
+
+__global__ __launch_bounds__(kThreads) void k_plan_accumulate(
+    const int32_t* __restrict__ pix, const float* __restrict__ wq, const float* __restrict__ wu,
+    const Tile* __restrict__ tiles, int64_t n_pix_global, double* __restrict__ B,
+    int32_t* __restrict__ hits, int32_t* __restrict__ err) {
+  const Tile tl = tiles[blockIdx.x];
+  const BjFlush flush{B, hits};
+  const double c0 = tl.c0;
+  for (int off = 0; off < tl.len; off += kThreads * 4) {
+    int key[4];
+    double v[4][7];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = off + threadIdx.x * 4 + j;
+      key[j] = -1;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) v[j][c] = 0.0;
+      if (o < tl.len) {
+        const int64_t i = tl.start + o;
+        int g = pix[i];
+        if (g < -1 || g >= n_pix_global) {
+          atomicOr(err, 1);
+          g = -1;
+        }
+        key[j] = g;
+        const double q = wq[i], u = wu[i];
+        v[j][0] = c0;
+        v[j][1] = c0 * q;
+        v[j][2] = c0 * u;
+        v[j][3] = c0 * q * q;
+        v[j][4] = c0 * q * u;
+        v[j][5] = c0 * u * u;
+        v[j][6] = 1.0;
+      }
+    }
+    wave_merge_runs<7>(key, v, flush);
+  }
+}
+
+// ---- per-pixel classification: keep when hits >= 3 and cond(B) <= cond_max ----------------
+
+// Eigenvalues of a symmetric 3x3 matrix by cyclic Jacobi rotations (FP64).
+__device__ void sym3_eigs(const double* b6, double& lo, double& hi) {
+  double a[3][3] = {{b6[0], b6[1], b6[2]}, {b6[1], b6[3], b6[4]}, {b6[2], b6[4], b6[5]}};
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double diag = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off <= 1e-34 * diag) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      for (int k = 0; k < 3; ++k) {  // A <- A J  (columns p, q)
+        const double akp = a[k][p], akq = a[k][q];
+        a[k][p] = c * akp - s * akq;
+        a[k][q] = s * akp + c * akq;
+      }
+      for (int k = 0; k < 3; ++k) {  // A <- J^T A  (rows p, q)
+        const double apk = a[p][k], aqk = a[q][k];
+        a[p][k] = c * apk - s * aqk;
+        a[q][k] = s * apk + c * aqk;
+      }
+    }
+  }
+  lo = fmin(a[0][0], fmin(a[1][1], a[2][2]));
+  hi = fmax(a[0][0], fmax(a[1][1], a[2][2]));
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_classify(const double* __restrict__ B,
+                                                            const int32_t* __restrict__ hits,
+                                                            int64_t n, double cond_max,
+                                                            uint8_t* __restrict__ keep,
+                                                            unsigned long long* __restrict__ n_obs) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  int observed = 0;
+  if (g < n) {
+    const int h = hits[g];
+    uint8_t k = 0;
+    if (h > 0) {
+      observed = 1;
+      if (h >= 3) {
+        double lo, hi;
+        sym3_eigs(B + 6 * g, lo, hi);
+        if (lo > 0.0 && hi <= cond_max * lo) k = 1;
+      }
+    }
+    keep[g] = k;
+  }
+  const unsigned long long cnt = __ballot(observed);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(n_obs, static_cast<unsigned long long>(__popcll(cnt)));
+}
+
+// ---- compaction: prefix sum of keep flags --------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_scan_count(const uint8_t* __restrict__ keep,
+                                                         int64_t n, int32_t* __restrict__ counts) {
+  __shared__ int red[kThreads / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  int c = 0;
+  for (int i = threadIdx.x; i < kScanChunk; i += kThreads) {
+    const int64_t g = base + i;
+    if (g < n) c += keep[g];
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    counts[blockIdx.x] = s;
+  }
+}
+
+// Exclusive scan of the per-chunk counts by one workgroup; the total goes to *total.
+__global__ __launch_bounds__(1024) void k_scan_offsets(int32_t* __restrict__ counts, int n,
+                                                       int64_t* __restrict__ total) {
+  __shared__ int64_t part[1024];
+  const int per = (n + 1023) / 1024;
+  const int lo = threadIdx.x * per, hi = min(n, lo + per);
+  int64_t s = 0;
+  for (int i = lo; i < hi; ++i) s += counts[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int64_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int i = lo; i < hi; ++i) {
+    const int32_t v = counts[i];
+    counts[i] = static_cast<int32_t>(run);
+    run += v;
+  }
+}
+
+// Local ids for kept pixels; kept ids, hits and inverted BJ blocks in local order.
+__global__ __launch_bounds__(kThreads) void k_scan_write(
+    const uint8_t* __restrict__ keep, int64_t n, const int32_t* __restrict__ offsets,
+    const double* __restrict__ B, const int32_t* __restrict__ hits_g, int32_t* __restrict__ local,
+    int64_t* __restrict__ kept_ids, int32_t* __restrict__ hits, double* __restrict__ minv) {
+  __shared__ int wsum[kThreads / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  int run = offsets[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < kScanChunk; i0 += kThreads) {
+    const int64_t g = base + i0 + threadIdx.x;
+    const int k = (g < n) ? keep[g] : 0;
+    const unsigned long long m = __ballot(k);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wave; ++w) woff += wsum[w];
+    int tot = 0;
+    for (int w = 0; w < kThreads / 64; ++w) tot += wsum[w];
+    if (g < n) {
+      if (k) {
+        const int l = run + woff + before;
+        local[g] = l;
+        kept_ids[l] = g;
+        hits[l] = hits_g[g];
+        const double* b = B + 6 * g;
+        const double a = b[0], bb = b[1], c = b[2], d = b[3], e = b[4], f = b[5];
+        const double A00 = d * f - e * e, A01 = c * e - bb * f, A02 = bb * e - c * d;
+        const double A11 = a * f - c * c, A12 = bb * c - a * e, A22 = a * d - bb * bb;
+        const double inv = 1.0 / (a * A00 + bb * A01 + c * A02);
+        double* mo = minv + 6 * static_cast<int64_t>(l);
+        mo[0] = A00 * inv;
+        mo[1] = A01 * inv;
+        mo[2] = A02 * inv;
+        mo[3] = A11 * inv;
+        mo[4] = A12 * inv;
+        mo[5] = A22 * inv;
+      } else {
+        local[g] = -1;
+      }
+    }
+    run += tot;
+    __syncthreads();
+  }
+}
+
+// lpix[s] = local id of pix[s] (or -1); counts gap samples.
+__global__ __launch_bounds__(kThreads) void k_plan_remap(const int32_t* __restrict__ pix,
+                                                         const int32_t* __restrict__ local,
+                                                         int32_t* __restrict__ lpix, int64_t n,
+                                                         unsigned long long* __restrict__ n_gap) {
+  int gaps = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int g = pix[i];
+    const int l = g >= 0 ? local[g] : -1;
+    lpix[i] = l;
+    gaps += (l < 0);
+  }
+  for (int o = 32; o > 0; o >>= 1) gaps += __shfl_down(gaps, o);
+  if ((threadIdx.x & 63) == 0 && gaps) atomicAdd(n_gap, static_cast<unsigned long long>(gaps));
+}
+
+// ---- band symbols f(w) = c_0 + 2 sum_k c_k cos(k w) on an M-point grid (Clenshaw, FP64) -----
+
+__global__ __launch_bounds__(kThreads) void k_band_symbol(
+    const float* __restrict__ coef, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ ncoef, int M, int fft_n, float* __restrict__ spec,
+    double* __restrict__ block_min) {
+  extern __shared__ float cs[];
+  __shared__ double red[kThreads / 64];
+  const int band = blockIdx.y;
+  const int nc = ncoef[band];
+  const float* c = coef + off[band];
+  for (int i = threadIdx.x; i < nc; i += kThreads) cs[i] = c[i];
+  __syncthreads();
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  double f = INFINITY;
+  if (k <= M / 2) {
+    const double x = cospi(2.0 * static_cast<double>(k) / static_cast<double>(M));
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = nc - 1; j >= 1; --j) {
+      const double b0 = 2.0 * static_cast<double>(cs[j]) + 2.0 * x * b1 - b2;
+      b2 = b1;
+      b1 = b0;
+    }
+    f = static_cast<double>(cs[0]) + x * b1 - b2;
+    if (spec != nullptr) {
+      const int step = M / fft_n;
+      if (k % step == 0) {
+        const int kk = k / step;  // 0 .. fft_n / 2
+        spec[static_cast<int64_t>(band) * (fft_n / 2 + 1) + kk] =
+            static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
+      }
+    }
+  }
+  double m = f;
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_down(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) r = fmin(r, red[w]);
+    block_min[static_cast<int64_t>(band) * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+template <class T>
+mm_status upload(Plan* P, T** dst, const std::vector<T>& h) {
+  MM_TRY(dalloc(P, dst, h.size()));
+  if (!h.empty()) MM_HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MM_OK;
+}
+
+// Temporary device buffer freed at scope exit.
+template <class T>
+struct Scratch {
+  T* p = nullptr;
+  ~Scratch() {
+    if (p) (void)hipFree(p);
+  }
+  mm_status alloc(size_t n) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(MM_ERR_OOM, std::string("hipMalloc (plan scratch): ") + hipGetErrorString(e));
+    }
+    return MM_OK;
+  }
+};
+
+mm_status validate(const mm_geometry* g, std::vector<int>& order, int32_t& lambda_max) {
+  if (g->n_samples < 0) return fail(MM_ERR_INVALID, "n_samples < 0");
+  if (g->n_samples > (int64_t(1) << 40)) return fail(MM_ERR_INVALID, "n_samples too large");
+  if (g->n_pix_global < 0 || g->n_pix_global > INT32_MAX)
+    return fail(MM_ERR_INVALID, "n_pix_global out of [0, 2^31)");
+  if (g->n_samples > 0 && (!g->pix || !g->w_q || !g->w_u))
+    return fail(MM_ERR_INVALID, "pix / w_q / w_u must be device pointers");
+  if (g->n_blocks < 0 || g->n_bands < 0) return fail(MM_ERR_INVALID, "negative table size");
+  if (g->n_blocks > 0 && (!g->blk_start || !g->blk_len || !g->blk_band))
+    return fail(MM_ERR_INVALID, "block table pointers are NULL");
+  if (g->n_bands > 0 && (!g->band_ncoef || !g->band_offset || !g->band_coef))
+    return fail(MM_ERR_INVALID, "band table pointers are NULL");
+  if (g->n_blocks > 0 && g->n_bands == 0) return fail(MM_ERR_INVALID, "blocks without bands");
+  lambda_max = 0;
+  for (int b = 0; b < g->n_bands; ++b) {
+    if (g->band_ncoef[b] < 1) return fail(MM_ERR_INVALID, "band_ncoef < 1");
+    if (g->band_offset[b] < 0) return fail(MM_ERR_INVALID, "band_offset < 0");
+  }
+  std::vector<char> used(static_cast<size_t>(g->n_bands), 0);
+  for (int i = 0; i < g->n_blocks; ++i) {
+    const int64_t s = g->blk_start[i], L = g->blk_len[i];
+    const int b = g->blk_band[i];
+    if (s < 0 || L < 1 || s + L > g->n_samples)
+      return fail(MM_ERR_INVALID, "block " + std::to_string(i) + " outside [0, n_samples)");
+    if (L > INT32_MAX) return fail(MM_ERR_INVALID, "block longer than 2^31 samples");
+    if (b < 0 || b >= g->n_bands) return fail(MM_ERR_INVALID, "block band index out of range");
+    used[b] = 1;
+  }
+  for (int b = 0; b < g->n_bands; ++b)
+    if (used[b]) lambda_max = std::max(lambda_max, g->band_ncoef[b] - 1);
+  order.resize(g->n_blocks);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return g->blk_start[a] < g->blk_start[b]; });
+  for (size_t i = 1; i < order.size(); ++i) {
+    const int a = order[i - 1], b = order[i];
+    if (g->blk_start[a] + g->blk_len[a] > g->blk_start[b])
+      return fail(MM_ERR_INVALID, "blocks overlap");
+  }
+  if (g->det_offset != nullptr && g->n_dets > 0) {
+    if (g->det_offset[0] != 0 || g->det_offset[g->n_dets] != g->n_samples)
+      return fail(MM_ERR_INVALID, "det_offset must span [0, n_samples]");
+    for (int d = 0; d < g->n_dets; ++d)
+      if (g->det_offset[d + 1] < g->det_offset[d])
+        return fail(MM_ERR_INVALID, "det_offset not ascending");
+    for (int i = 0; i < g->n_blocks; ++i) {
+      const int64_t s = g->blk_start[i], e = s + g->blk_len[i];
+      const int64_t* it = std::upper_bound(g->det_offset, g->det_offset + g->n_dets + 1, s);
+      const int64_t det_end = *it;
+      if (e > det_end) return fail(MM_ERR_INVALID, "block crosses a detector boundary");
+    }
+  }
+  return MM_OK;
+}
+
+}  // namespace
+
+void destroy_plan(Plan* P) {
+  if (!P) return;
+  void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
+                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->id_seg, P->t, P->u,
+                  P->r, P->z, P->p, P->q, P->b, P->partial, P->state};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (P->h_state) (void)hipHostFree(P->h_state);
+  for (int k = 0; k < K_NKINDS; ++k)
+    for (hipEvent_t e : P->timing.pending[k]) (void)hipEventDestroy(e);
+  delete P;
+}
+
+mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
+  *out = nullptr;
+  std::vector<int> order;
+  int32_t lambda_max = 0;
+  MM_TRY(validate(g, order, lambda_max));
+
+  // Algorithm selection.
+  int32_t algo = g->toeplitz_algo;
+  int32_t fft_n = 0;
+  if (algo != MM_TOEPLITZ_AUTO && algo != MM_TOEPLITZ_DIRECT && algo != MM_TOEPLITZ_FFT)
+    return fail(MM_ERR_INVALID, "unknown toeplitz_algo");
+  if (algo == MM_TOEPLITZ_AUTO) algo = (lambda_max <= 32) ? MM_TOEPLITZ_DIRECT : MM_TOEPLITZ_FFT;
+  if (algo == MM_TOEPLITZ_FFT) {
+    fft_n = g->fft_size > 0 ? g->fft_size : choose_fft_size(lambda_max);
+    if (fft_n == 0 || !fft_size_supported(fft_n))
+      return fail(MM_ERR_UNSUPPORTED, "no supported FFT size for lambda = " + std::to_string(lambda_max));
+    if (fft_n <= 2 * lambda_max) return fail(MM_ERR_INVALID, "fft_size must exceed 2 lambda");
+  } else if (lambda_max > max_direct_lambda()) {
+    return fail(MM_ERR_UNSUPPORTED, "direct product limited to lambda <= " +
+                                        std::to_string(max_direct_lambda()));
+  }
+
+  Plan* P = new Plan();
+  struct Guard {
+    Plan*& p;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) destroy_plan(p);
+    }
+  } guard{P};
+  MM_HIP_TRY(hipGetDevice(&P->device));
+  P->n_samples = g->n_samples;
+  P->n_pix_global = g->n_pix_global;
+  P->lambda_max = lambda_max;
+  P->algo = algo;
+  P->fft_n = fft_n;
+  P->n_blocks = g->n_blocks;
+  P->n_bands = g->n_bands;
+  const int64_t n = g->n_samples;
+  const int64_t ng = g->n_pix_global;
+
+  // ---- segment tables: blocks and identity gaps ------------------------------------------
+  std::vector<Tile> tiles;
+  std::vector<int64_t> idseg;
+  auto add_tiles = [&](int64_t s0, int64_t len, float c0) {
+    for (int64_t o = 0; o < len; o += kTile)
+      tiles.push_back(Tile{s0 + o, static_cast<int32_t>(std::min<int64_t>(kTile, len - o)), c0});
+  };
+  auto add_identity = [&](int64_t s0, int64_t len) {
+    add_tiles(s0, len, 1.0f);
+    for (int64_t o = 0; o < len; o += 65536) {
+      idseg.push_back(s0 + o);
+      idseg.push_back(std::min<int64_t>(65536, len - o));
+    }
+  };
+  int64_t cursor = 0;
+  for (int i : order) {
+    const int64_t s0 = g->blk_start[i], len = g->blk_len[i];
+    if (s0 > cursor) add_identity(cursor, s0 - cursor);
+    const int b = g->blk_band[i];
+    add_tiles(s0, len, g->band_coef[g->band_offset[b]]);
+    cursor = s0 + len;
+  }
+  if (cursor < n) add_identity(cursor, n - cursor);
+
+  std::vector<Chunk> chunks;
+  if (algo == MM_TOEPLITZ_FFT) {
+    const int64_t L = fft_n - 2 * lambda_max;
+    for (int i : order) {
+      const int64_t s0 = g->blk_start[i], len = g->blk_len[i];
+      for (int64_t o = 0; o < len; o += L)
+        chunks.push_back(Chunk{s0 + o, s0, static_cast<int32_t>(len),
+                               static_cast<int32_t>(std::min<int64_t>(L, len - o)),
+                               g->blk_band[i], 0});
+    }
+  } else {
+    for (int i : order) {
+      const int64_t s0 = g->blk_start[i], len = g->blk_len[i];
+      for (int64_t o = 0; o < len; o += 1024)
+        chunks.push_back(Chunk{s0 + o, s0, static_cast<int32_t>(len),
+                               static_cast<int32_t>(std::min<int64_t>(1024, len - o)),
+                               g->blk_band[i], 0});
+    }
+  }
+  if (chunks.size() > static_cast<size_t>(INT32_MAX) || idseg.size() / 2 > static_cast<size_t>(INT32_MAX))
+    return fail(MM_ERR_UNSUPPORTED, "too many segments");
+  P->n_chunks = static_cast<int32_t>(chunks.size());
+  P->n_id_seg = static_cast<int32_t>(idseg.size() / 2);
+  P->h_id_seg = idseg;
+  MM_TRY(upload(P, &P->chunks, chunks));
+  MM_TRY(upload(P, &P->id_seg, idseg));
+
+  // ---- bands -------------------------------------------------------------------------------
+  int64_t n_coef_total = 0;
+  for (int b = 0; b < g->n_bands; ++b)
+    n_coef_total = std::max<int64_t>(n_coef_total, g->band_offset[b] + g->band_ncoef[b]);
+  {
+    std::vector<float> coef(g->band_coef, g->band_coef + n_coef_total);
+    std::vector<int64_t> off(g->band_offset, g->band_offset + g->n_bands);
+    std::vector<int32_t> nc(g->band_ncoef, g->band_ncoef + g->n_bands);
+    MM_TRY(upload(P, &P->band_coef, coef));
+    MM_TRY(upload(P, &P->band_off, off));
+    MM_TRY(upload(P, &P->band_ncoef, nc));
+  }
+
+  // ---- pointing copies + global accumulation -------------------------------------------------
+  MM_TRY(dalloc(P, &P->lpix, n));
+  MM_TRY(dalloc(P, &P->wq, n));
+  MM_TRY(dalloc(P, &P->wu, n));
+  if (n > 0) {
+    MM_HIP_TRY(hipMemcpyAsync(P->wq, g->w_q, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    MM_HIP_TRY(hipMemcpyAsync(P->wu, g->w_u, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  Scratch<double> Bg;
+  Scratch<int32_t> hits_g, local, counts, err;
+  Scratch<uint8_t> keep;
+  Scratch<Tile> dtiles;
+  Scratch<unsigned long long> ctr;  // [0] observed, [1] gap samples
+  Scratch<int64_t> total;
+  MM_TRY(Bg.alloc(6 * std::max<int64_t>(ng, 1)));
+  MM_TRY(hits_g.alloc(std::max<int64_t>(ng, 1)));
+  MM_TRY(local.alloc(ng));
+  MM_TRY(keep.alloc(ng));
+  MM_TRY(err.alloc(1));
+  MM_TRY(ctr.alloc(2));
+  MM_TRY(total.alloc(1));
+  MM_TRY(dtiles.alloc(tiles.size()));
+  const int n_scan = static_cast<int>((ng + kScanChunk - 1) / kScanChunk);
+  MM_TRY(counts.alloc(n_scan + 1));
+  MM_HIP_TRY(hipMemsetAsync(Bg.p, 0, sizeof(double) * 6 * std::max<int64_t>(ng, 1), s));
+  MM_HIP_TRY(hipMemsetAsync(hits_g.p, 0, sizeof(int32_t) * std::max<int64_t>(ng, 1), s));
+  MM_HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+  MM_HIP_TRY(hipMemsetAsync(ctr.p, 0, 2 * sizeof(unsigned long long), s));
+  MM_HIP_TRY(hipMemsetAsync(total.p, 0, sizeof(int64_t), s));
+  if (!tiles.empty()) {
+    MM_HIP_TRY(hipMemcpyAsync(dtiles.p, tiles.data(), tiles.size() * sizeof(Tile),
+                              hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_plan_accumulate, dim3(static_cast<unsigned>(tiles.size())), dim3(kThreads),
+                       0, s, g->pix, g->w_q, g->w_u, dtiles.p, ng, Bg.p, hits_g.p, err.p);
+    MM_HIP_TRY(hipGetLastError());
+  }
+  int32_t h_err = 0;
+  MM_HIP_TRY(hipMemcpyAsync(&h_err, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  if (h_err) return fail(MM_ERR_INVALID, "pixel index out of [-1, n_pix_global)");
+
+  // ---- classify + compact --------------------------------------------------------------------
+  const double cond_max = g->cond_max > 0 ? g->cond_max : 1.0e3;
+  if (ng > 0) {
+    hipLaunchKernelGGL(k_plan_classify, dim3(static_cast<unsigned>((ng + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, Bg.p, hits_g.p, ng, cond_max, keep.p, ctr.p);
+    MM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_count, dim3(n_scan), dim3(kThreads), 0, s, keep.p, ng, counts.p);
+    MM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, counts.p, n_scan, total.p);
+    MM_HIP_TRY(hipGetLastError());
+  }
+  int64_t n_kept = 0;
+  unsigned long long h_ctr[2] = {0, 0};
+  MM_HIP_TRY(hipMemcpyAsync(&n_kept, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipMemcpyAsync(h_ctr, ctr.p, sizeof(h_ctr), hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  P->n_kept = n_kept;
+  P->n_obs = static_cast<int64_t>(h_ctr[0]);
+  MM_TRY(dalloc(P, &P->kept_ids, n_kept));
+  MM_TRY(dalloc(P, &P->hits, n_kept));
+  MM_TRY(dalloc(P, &P->minv, 6 * n_kept));
+  if (ng > 0) {
+    hipLaunchKernelGGL(k_scan_write, dim3(n_scan), dim3(kThreads), 0, s, keep.p, ng, counts.p,
+                       Bg.p, hits_g.p, local.p, P->kept_ids, P->hits, P->minv);
+    MM_HIP_TRY(hipGetLastError());
+  }
+  if (n > 0) {
+    int64_t gr = (n + kThreads - 1) / kThreads;
+    if (gr > 65536) gr = 65536;
+    hipLaunchKernelGGL(k_plan_remap, dim3(static_cast<unsigned>(gr)), dim3(kThreads), 0, s, g->pix,
+                       local.p, P->lpix, n, ctr.p + 1);
+    MM_HIP_TRY(hipGetLastError());
+  }
+
+  // ---- band symbols: positivity on a grid of >= 8 lambda points; FFT spectra ----------------
+  if (g->n_bands > 0) {
+    int M = 16;
+    while (M < 8 * lambda_max) M *= 2;
+    if (fft_n > M) M = fft_n;
+    if (algo == MM_TOEPLITZ_FFT) MM_TRY(dalloc(P, &P->spec, static_cast<size_t>(g->n_bands) * (fft_n / 2 + 1)));
+    const int gx = (M / 2 + 1 + kThreads - 1) / kThreads;
+    Scratch<double> mins;
+    MM_TRY(mins.alloc(static_cast<size_t>(gx) * g->n_bands));
+    int max_nc = 1;
+    for (int b = 0; b < g->n_bands; ++b) max_nc = std::max(max_nc, g->band_ncoef[b]);
+    const size_t lds = sizeof(float) * max_nc;
+    if (lds > 64 * 1024) return fail(MM_ERR_UNSUPPORTED, "band too long for the symbol kernel");
+    hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), lds, s, P->band_coef,
+                       P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
+    MM_HIP_TRY(hipGetLastError());
+    std::vector<double> h_mins(static_cast<size_t>(gx) * g->n_bands);
+    MM_HIP_TRY(hipMemcpyAsync(h_mins.data(), mins.p, h_mins.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    for (int b = 0; b < g->n_bands; ++b) {
+      double m = INFINITY;
+      for (int x = 0; x < gx; ++x) m = std::min(m, h_mins[static_cast<size_t>(b) * gx + x]);
+      if (!(m > 0.0))
+        return fail(MM_ERR_NOT_SPD, "band " + std::to_string(b) + " has a non-positive symbol (" +
+                                        std::to_string(m) + ")");
+    }
+  }
+  if (algo == MM_TOEPLITZ_FFT) {
+    std::vector<float2> t0(128), t1(fft_n / 128);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int m = 0; m < 128; ++m) {
+      const double a = -two_pi * m / fft_n;
+      t0[m] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
+    }
+    for (int m = 0; m < fft_n / 128; ++m) {
+      const double a = -two_pi * (128.0 * m) / fft_n;
+      t1[m] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
+    }
+    MM_TRY(upload(P, &P->tw0, t0));
+    MM_TRY(upload(P, &P->tw1, t1));
+  }
+
+  // ---- workspace -----------------------------------------------------------------------------
+  MM_TRY(dalloc(P, &P->t, n));
+  MM_TRY(dalloc(P, &P->u, n));
+  const int64_t nu = 3 * n_kept;
+  MM_TRY(dalloc(P, &P->r, nu));
+  MM_TRY(dalloc(P, &P->z, nu));
+  MM_TRY(dalloc(P, &P->p, nu));
+  MM_TRY(dalloc(P, &P->q, nu));
+  MM_TRY(dalloc(P, &P->b, nu));
+  int64_t nrb = (n_kept + 1023) / 1024;
+  if (nrb < 1) nrb = 1;
+  if (nrb > 1024) nrb = 1024;
+  P->n_red_blocks = static_cast<int32_t>(nrb);
+  MM_TRY(dalloc(P, &P->partial, 4 * nrb));
+  MM_TRY(dalloc(P, &P->state, 1));
+  MM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->h_state), sizeof(CgState), hipHostMallocDefault));
+
+  unsigned long long h_gap = 0;
+  MM_HIP_TRY(hipMemcpyAsync(&h_gap, ctr.p + 1, sizeof(h_gap), hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  P->n_gap = static_cast<int64_t>(h_gap);
+  guard.keep = true;
+  *out = P;
+  return MM_OK;
+}
+
+}  // namespace mm

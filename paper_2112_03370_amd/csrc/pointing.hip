@@ -1,0 +1,222 @@
+// Pointing products on the GPU: un-pointing t = P x and pointing y = P^T u (MAPMAT core
+// operations), plus the data mask used for the right-hand side.
+//
+// Layout: per-sample arrays are separate coalesced streams (local pixel int32, cos/sin FP32);
+// each thread owns 4 consecutive samples so every stream is read with one 16-byte load.
+// Pixel-domain vectors are FP64 [n_kept][3] and stay cache-resident while the time streams go
+// by.  P^T accumulates in FP64: samples of one pixel arrive in runs (the scan dwells on a pixel
+// for several samples), so each thread first sums its own run pieces, then a wavefront
+// segmented scan merges runs that continue across lanes, and only the lane that closes a run
+// issues the three FP64 atomic adds.
+#include "mm_internal.h"
+#include "wave_runs.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 4;
+constexpr int kPerBlock = kThreads * kPerThread;
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + kPerBlock - 1) / kPerBlock;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<int>(g);
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpoint(const int32_t* __restrict__ lpix,
+                                                      const float* __restrict__ wq,
+                                                      const float* __restrict__ wu,
+                                                      const double* __restrict__ x,
+                                                      float* __restrict__ t, int64_t n,
+                                                      const int32_t* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kPerThread;
+       i0 < n; i0 += static_cast<int64_t>(gridDim.x) * kPerBlock) {
+    if (i0 + kPerThread <= n) {
+      const int4 k4 = *reinterpret_cast<const int4*>(lpix + i0);
+      const float4 q4 = *reinterpret_cast<const float4*>(wq + i0);
+      const float4 u4 = *reinterpret_cast<const float4*>(wu + i0);
+      const int key[4] = {k4.x, k4.y, k4.z, k4.w};
+      const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
+      const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+      float out[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double v = 0.0;
+        if (key[j] >= 0) {
+          const double* m = x + 3 * static_cast<int64_t>(key[j]);
+          v = m[0] + static_cast<double>(qq[j]) * m[1] + static_cast<double>(uu[j]) * m[2];
+        }
+        out[j] = static_cast<float>(v);
+      }
+      *reinterpret_cast<float4*>(t + i0) = make_float4(out[0], out[1], out[2], out[3]);
+    } else {
+      for (int64_t i = i0; i < n; ++i) {
+        const int k = lpix[i];
+        double v = 0.0;
+        if (k >= 0) {
+          const double* m = x + 3 * static_cast<int64_t>(k);
+          v = m[0] + static_cast<double>(wq[i]) * m[1] + static_cast<double>(wu[i]) * m[2];
+        }
+        t[i] = static_cast<float>(v);
+      }
+    }
+  }
+}
+
+// Scalar variant for unaligned caller buffers.
+__global__ __launch_bounds__(kThreads) void k_unpoint_scalar(const int32_t* __restrict__ lpix,
+                                                             const float* __restrict__ wq,
+                                                             const float* __restrict__ wu,
+                                                             const double* __restrict__ x,
+                                                             float* __restrict__ t, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int k = lpix[i];
+    double v = 0.0;
+    if (k >= 0) {
+      const double* m = x + 3 * static_cast<int64_t>(k);
+      v = m[0] + static_cast<double>(wq[i]) * m[1] + static_cast<double>(wu[i]) * m[2];
+    }
+    t[i] = static_cast<float>(v);
+  }
+}
+
+// t = d at kept samples, 0 at gap samples (flagged or excised: zero rows of P).
+__global__ __launch_bounds__(kThreads) void k_mask_data(const int32_t* __restrict__ lpix,
+                                                        const float* __restrict__ d,
+                                                        float* __restrict__ t, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    t[i] = lpix[i] >= 0 ? d[i] : 0.0f;
+  }
+}
+
+struct PointFlush {
+  double* y;
+  __device__ void operator()(int key, const double (&v)[3]) const {
+    double* dst = y + 3 * static_cast<int64_t>(key);
+    unsafeAtomicAdd(dst + 0, v[0]);
+    unsafeAtomicAdd(dst + 1, v[1]);
+    unsafeAtomicAdd(dst + 2, v[2]);
+  }
+};
+
+template <bool kVec>
+__global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ lpix,
+                                                    const float* __restrict__ wq,
+                                                    const float* __restrict__ wu,
+                                                    const float* __restrict__ u,
+                                                    double* __restrict__ y, int64_t n,
+                                                    const int32_t* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const PointFlush flush{y};
+  // Every lane of the block runs the same number of iterations (wavefront-collective scan).
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kPerBlock; base < n;
+       base += static_cast<int64_t>(gridDim.x) * kPerBlock) {
+    const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kPerThread;
+    int key[4] = {-1, -1, -1, -1};
+    double v[4][3];
+    if (kVec && i0 + kPerThread <= n) {
+      const int4 k4 = *reinterpret_cast<const int4*>(lpix + i0);
+      const float4 q4 = *reinterpret_cast<const float4*>(wq + i0);
+      const float4 w4 = *reinterpret_cast<const float4*>(wu + i0);
+      const float4 t4 = *reinterpret_cast<const float4*>(u + i0);
+      key[0] = k4.x; key[1] = k4.y; key[2] = k4.z; key[3] = k4.w;
+      const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
+      const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+      const float tt[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double tv = tt[j];
+        v[j][0] = tv;
+        v[j][1] = static_cast<double>(qq[j]) * tv;
+        v[j][2] = static_cast<double>(ww[j]) * tv;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t i = i0 + j;
+        v[j][0] = v[j][1] = v[j][2] = 0.0;
+        if (i < n) {
+          key[j] = lpix[i];
+          const double tv = u[i];
+          v[j][0] = tv;
+          v[j][1] = static_cast<double>(wq[i]) * tv;
+          v[j][2] = static_cast<double>(wu[i]) * tv;
+        }
+      }
+    }
+    wave_merge_runs<3>(key, v, flush);
+  }
+}
+
+__global__ void k_zero(double* __restrict__ y, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = 0.0;
+}
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+mm_status launch_zero(double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return MM_OK;
+  int64_t g = (n + 255) / 256;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, y, n);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+mm_status launch_unpoint(Plan* P, const double* x, float* t, const int32_t* done,
+                         hipStream_t s) {
+  const int64_t n = P->n_samples;
+  if (n == 0) return MM_OK;
+  TimedLaunch tl(P, K_UNPOINT, s);
+  if (aligned16(t)) {
+    hipLaunchKernelGGL(k_unpoint, dim3(grid_for(n)), dim3(kThreads), 0, s, P->lpix, P->wq, P->wu,
+                       x, t, n, done);
+  } else {
+    int64_t g = (n + kThreads - 1) / kThreads;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_unpoint_scalar, dim3(static_cast<unsigned>(g)), dim3(kThreads), 0, s,
+                       P->lpix, P->wq, P->wu, x, t, n);
+  }
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+mm_status launch_mask_data(Plan* P, const float* d, float* t, hipStream_t s) {
+  const int64_t n = P->n_samples;
+  if (n == 0) return MM_OK;
+  int64_t g = (n + kThreads - 1) / kThreads;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_mask_data, dim3(static_cast<unsigned>(g)), dim3(kThreads), 0, s, P->lpix,
+                     d, t, n);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, const int32_t* done,
+                       hipStream_t s) {
+  if (zero_first) MM_TRY(launch_zero(y, 3 * P->n_kept, s));
+  const int64_t n = P->n_samples;
+  if (n == 0 || P->n_kept == 0) return MM_OK;
+  TimedLaunch tl(P, K_POINT, s);
+  if (aligned16(u)) {
+    hipLaunchKernelGGL(k_point<true>, dim3(grid_for(n)), dim3(kThreads), 0, s, P->lpix, P->wq,
+                       P->wu, u, y, n, done);
+  } else {
+    hipLaunchKernelGGL(k_point<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, P->lpix, P->wq,
+                       P->wu, u, y, n, done);
+  }
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace mm

@@ -1,0 +1,295 @@
+"""Python binding of the HIP map-making library (libmm.so) -- argument marshalling only.
+
+Every computation runs in the library's kernels; torch is used for device memory and streams.
+Names follow the C ABI in include/mm.h.  Loading fails loudly when the library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm.so")
+
+MM_OK = 0
+MM_PENDING = 1
+STATUS = {
+    0: "MM_OK", 1: "MM_PENDING", -1: "MM_ERR_INVALID", -2: "MM_ERR_NOT_SPD",
+    -3: "MM_ERR_NO_CONV", -4: "MM_ERR_OOM", -5: "MM_ERR_HIP", -6: "MM_ERR_BUDGET",
+    -7: "MM_ERR_UNSUPPORTED", -8: "MM_ERR_NOT_FOUND",
+}
+TOEPLITZ_AUTO, TOEPLITZ_DIRECT, TOEPLITZ_FFT = 0, 1, 2
+KIND_UNPOINT, KIND_TOEPLITZ, KIND_POINT, KIND_CG = 0, 1, 2, 3
+
+_c_i32, _c_i64, _c_dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class MMError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("n_samples", _c_i64), ("pix", _vp), ("w_q", _vp), ("w_u", _vp),
+        ("n_pix_global", _c_i64), ("n_blocks", _c_i32), ("blk_start", _vp), ("blk_len", _vp),
+        ("blk_band", _vp), ("n_bands", _c_i32), ("band_ncoef", _vp), ("band_offset", _vp),
+        ("band_coef", _vp), ("n_dets", _c_i32), ("det_offset", _vp), ("cond_max", _c_dbl),
+        ("toeplitz_algo", _c_i32), ("fft_size", _c_i32),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_samples", _c_i64), ("n_pix_global", _c_i64), ("n_obs", _c_i64), ("n_kept", _c_i64),
+        ("n_excised", _c_i64), ("n_gap_samples", _c_i64), ("device_bytes", _c_i64),
+        ("lambda_max", _c_i32), ("toeplitz_algo", _c_i32), ("fft_size", _c_i32),
+        ("n_blocks", _c_i32), ("n_chunks", _c_i32),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", _c_dbl), ("max_iter", _c_i32), ("use_x0", _c_i32),
+                ("check_every", _c_i32), ("use_graph", _c_i32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", _c_i32), ("converged", _c_i32), ("relres", _c_dbl),
+                ("true_relres", _c_dbl), ("bnorm", _c_dbl), ("ms", _c_dbl)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libmm.so (raises FileNotFoundError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} not found: build it with `python -m paper_2112_03370_amd.build`")
+    lib = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    sigs = {
+        "mm_plan": [P(Geometry), _vp, P(_vp)],
+        "mm_plan_destroy": [_vp],
+        "mm_plan_info": [_vp, P(PlanInfo)],
+        "mm_plan_pixels": [_vp, _vp, _vp],
+        "mm_unpoint": [_vp, _vp, _vp, _vp],
+        "mm_noise_weight": [_vp, _vp, _vp, _vp],
+        "mm_point": [_vp, _vp, _vp, _vp],
+        "mm_rhs": [_vp, _vp, _c_i32, _c_i64, _vp, _vp],
+        "mm_apply_A": [_vp, _vp, _vp, _c_i32, _vp],
+        "mm_precond_bj": [_vp, _vp, _vp, _c_i32, _vp],
+        "mm_pcg_solve": [_vp, _vp, _c_i32, _c_i64, _vp, P(SolveOpts), P(SolveInfo), _vp],
+        "mm_set_timing": [_vp, _c_i32],
+        "mm_kernel_time": [_vp, _c_i32, P(_c_dbl), P(_c_i64)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _c_i32
+    lib.mm_status_string.argtypes = [_c_i32]
+    lib.mm_status_string.restype = ctypes.c_char_p
+    lib.mm_last_error.argtypes = []
+    lib.mm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int, ok=(MM_OK,)):
+    if status not in ok:
+        raise MMError(status, (_lib.mm_last_error() or b"").decode())
+    return status
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class Plan:
+    """Device plan of one geometry.  Time-ordered inputs are torch CUDA tensors."""
+
+    def __init__(self, pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
+                 det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0,
+                 stream=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.device = pix.device
+        for name, t, dt in (("pix", pix, torch.int32), ("wq", wq, torch.float32),
+                            ("wu", wu, torch.float32)):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous CUDA {dt} tensor")
+        n = int(pix.numel())
+        if wq.numel() != n or wu.numel() != n:
+            raise ValueError("pix, wq, wu sizes differ")
+        self._bs = _host(blk_start, np.int64)
+        self._bl = _host(blk_len, np.int64)
+        self._bb = _host(blk_band, np.int32)
+        ncoef = np.array([len(b) for b in bands], np.int32)
+        off = np.zeros(len(bands), np.int64)
+        if len(bands) > 1:
+            off[1:] = np.cumsum(ncoef[:-1])
+        coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
+                else np.zeros(1, np.float32))
+        self._nc, self._off, self._coef = ncoef, off, np.ascontiguousarray(coef, np.float32)
+        self._det = None if det_offset is None else _host(det_offset, np.int64)
+        g = Geometry()
+        g.n_samples = n
+        g.pix, g.w_q, g.w_u = _ptr(pix), _ptr(wq), _ptr(wu)
+        g.n_pix_global = int(n_pix_global)
+        g.n_blocks = len(self._bs)
+        g.blk_start = self._bs.ctypes.data
+        g.blk_len = self._bl.ctypes.data
+        g.blk_band = self._bb.ctypes.data
+        g.n_bands = len(bands)
+        g.band_ncoef = ncoef.ctypes.data
+        g.band_offset = off.ctypes.data
+        g.band_coef = self._coef.ctypes.data
+        g.n_dets = 0 if self._det is None else len(self._det) - 1
+        g.det_offset = None if self._det is None else self._det.ctypes.data
+        g.cond_max = float(cond_max)
+        g.toeplitz_algo = int(toeplitz_algo)
+        g.fft_size = int(fft_size)
+        h = _vp()
+        self._h = None
+        check(lib.mm_plan(ctypes.byref(g), _stream(stream), ctypes.byref(h)))
+        self._h = h.value
+        self.info = self.plan_info()
+        self.n_kept = int(self.info["n_kept"])
+        self.n_samples = n
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda", **kw):
+        import torch
+        pix = torch.from_numpy(np.ascontiguousarray(prob.pix)).to(device)
+        wq = torch.from_numpy(np.ascontiguousarray(prob.wq)).to(device)
+        wu = torch.from_numpy(np.ascontiguousarray(prob.wu)).to(device)
+        return cls(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len, prob.blk_band,
+                   prob.bands, det_offset=prob.det_offset, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- queries -------------------------------------------------------------------------
+    def plan_info(self) -> dict:
+        inf = PlanInfo()
+        check(self._lib.mm_plan_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def pixels(self):
+        ids = np.zeros(max(1, self.n_kept), np.int64)
+        hits = np.zeros(max(1, self.n_kept), np.int32)
+        check(self._lib.mm_plan_pixels(self._h, ids.ctypes.data, hits.ctypes.data))
+        return ids[:self.n_kept], hits[:self.n_kept]
+
+    # ---- operators -------------------------------------------------------------------------
+    def _map(self, k=1):
+        import torch
+        return torch.empty((k, self.n_kept, 3) if k > 1 else (self.n_kept, 3), dtype=torch.float64,
+                           device=self.device)
+
+    def unpoint(self, x, t=None, stream=None):
+        import torch
+        t = t if t is not None else torch.empty(self.n_samples, dtype=torch.float32, device=self.device)
+        check(self._lib.mm_unpoint(self._h, _ptr(x), _ptr(t), _stream(stream)))
+        return t
+
+    def noise_weight(self, t, u=None, stream=None):
+        import torch
+        u = u if u is not None else torch.empty_like(t)
+        check(self._lib.mm_noise_weight(self._h, _ptr(t), _ptr(u), _stream(stream)))
+        return u
+
+    def point(self, u, y=None, stream=None):
+        y = y if y is not None else self._map()
+        check(self._lib.mm_point(self._h, _ptr(u), _ptr(y), _stream(stream)))
+        return y
+
+    def rhs(self, d, b=None, stream=None):
+        k = 1 if d.dim() == 1 else int(d.shape[0])
+        ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
+        b = b if b is not None else self._map(k)
+        check(self._lib.mm_rhs(self._h, _ptr(d), k, ld, _ptr(b), _stream(stream)))
+        return b
+
+    def apply_A(self, x, y=None, stream=None):
+        k = 1 if x.dim() == 2 else int(x.shape[0])
+        y = y if y is not None else self._map(k)
+        check(self._lib.mm_apply_A(self._h, _ptr(x), _ptr(y), k, _stream(stream)))
+        return y
+
+    def precond_bj(self, r, z=None, stream=None):
+        k = 1 if r.dim() == 2 else int(r.shape[0])
+        z = z if z is not None else self._map(k)
+        check(self._lib.mm_precond_bj(self._h, _ptr(r), _ptr(z), k, _stream(stream)))
+        return z
+
+    def pcg_solve(self, d, x=None, tol=1e-8, max_iter=10000, use_x0=False, check_every=0,
+                  use_graph=True, stream=None, raise_on_error=True):
+        k = 1 if d.dim() == 1 else int(d.shape[0])
+        ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
+        x = x if x is not None else self._map(k)
+        o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every,
+                      use_graph=int(use_graph))
+        infos = (SolveInfo * max(1, k))()
+        st = self._lib.mm_pcg_solve(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o), infos,
+                                    _stream(stream))
+        if raise_on_error:
+            check(st)
+        res = [infos[j].as_dict() for j in range(k)]
+        for r in res:
+            r["status"] = STATUS.get(st, st)
+        return x, (res[0] if k == 1 else res)
+
+    # ---- timing ------------------------------------------------------------------------------
+    def set_timing(self, enable: bool):
+        check(self._lib.mm_set_timing(self._h, int(enable)))
+
+    def kernel_time(self, kind: int):
+        ms = _c_dbl()
+        n = _c_i64()
+        check(self._lib.mm_kernel_time(self._h, int(kind), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def exported_symbols(header: Optional[str] = None) -> Sequence[str]:
+    """Function names declared in include/*.h (used by the ABI export test)."""
+    import glob
+    import re
+    inc = header or os.path.join(os.path.dirname(_HERE), "include")
+    names = []
+    for h in sorted(glob.glob(os.path.join(inc, "*.h"))):
+        src = open(h).read()
+        names += re.findall(r"^\s*(?:mm_status|const char\*)\s+(mm_\w+)\s*\(", src, re.M)
+    return names

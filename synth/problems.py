@@ -133,7 +133,7 @@ def inverse_noise_band(lam, fsample, sigma=1.0, fknee=1.0, alpha=-1.0, n_grid=No
     return c.astype(np.float32)
 
 
-def _noise_batch(rng, n_int, length, fsample, sigma, fknee, alpha):
+def _noise_batch(rng, n_int, length, fsample, sigma, fknee, alpha, workers=None):
     """``n_int`` independent realisations of ``length`` samples (drawn on 2*length, cropped)."""
     m = 2 * length
     f = np.fft.rfftfreq(m, d=1.0 / fsample)
@@ -144,7 +144,7 @@ def _noise_batch(rng, n_int, length, fsample, sigma, fknee, alpha):
     g = rng.standard_normal((n_int, f.size)) + 1j * rng.standard_normal((n_int, f.size))
     g[:, -1] = g[:, -1].real
     spec = g * amp
-    return sfft.irfft(spec, m, axis=1, workers=_workers())[:, :length]
+    return sfft.irfft(spec, m, axis=1, workers=workers or _workers())[:, :length]
 
 
 # --------------------------------------------------------------------------------------------
@@ -170,9 +170,11 @@ def _sky(cfg_id, n_rhs, n_pix):
 
 def _fill_data(d, pix, wq, wu, m_true, cfg_id, det_offset, interval, fsample, sigma, fknees,
                alpha, noise):
-    """d[j] = P m_j + n_j per detector, in FP64, stored FP32."""
+    """d[j] = P m_j + n_j per detector, in FP64, stored FP32 (detectors in parallel threads;
+    every detector draws from its own streams, so the bytes do not depend on the threading)."""
     n_rhs = d.shape[0]
-    for det in range(len(det_offset) - 1):
+
+    def one(det):
         s0, s1 = int(det_offset[det]), int(det_offset[det + 1])
         p = pix[s0:s1]
         ok = p >= 0
@@ -184,16 +186,23 @@ def _fill_data(d, pix, wq, wu, m_true, cfg_id, det_offset, interval, fsample, si
             sig = m[pp, 0] + q * m[pp, 1] + u * m[pp, 2]
             sig[~ok] = 0.0
             if noise != "none":
-                n = np.empty(s1 - s0)
                 L = interval if interval > 0 else (s1 - s0)
                 n_int = (s1 - s0 + L - 1) // L
                 fk = 0.0 if noise == "white" else float(fknees[det])
                 for i in range(n_int):
                     a, b = i * L, min((i + 1) * L, s1 - s0)
                     g = _rng(cfg_id, _S_NOISE, det, i, j)
-                    n[a:b] = _noise_batch(g, 1, b - a, fsample, sigma, fk, alpha)[0]
-                sig += n
+                    sig[a:b] += _noise_batch(g, 1, b - a, fsample, sigma, fk, alpha, workers=1)[0]
             d[j, s0:s1] = sig.astype(np.float32)
+
+    n_dets = len(det_offset) - 1
+    if n_dets <= 1 or det_offset[-1] < (1 << 16):
+        for det in range(n_dets):
+            one(det)
+        return
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(one, range(n_dets)))
 
 
 def _bands_for(lam, fsample, sigma, fknees, alpha, noise):

@@ -1,0 +1,78 @@
+"""The C ABI library loads and exports every declared symbol; the binding's structs match the
+header's layout (CPU only: no compute call is made)."""
+
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2112_03370_amd import mapmaker
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(mapmaker.LIB_PATH):
+        pytest.skip("libmm.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(mapmaker.LIB_PATH)
+    names = mapmaker.exported_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    mapmaker.load()
+    assert lib.mm_status_string  # callable without a device
+
+
+def test_status_strings_without_device():
+    if not os.path.exists(mapmaker.LIB_PATH):
+        pytest.skip("libmm.so not built")
+    lib = mapmaker.load()
+    assert lib.mm_status_string(0) == b"MM_OK"
+    assert lib.mm_status_string(-2) == b"MM_ERR_NOT_SPD"
+    # argument validation happens before any device call
+    assert lib.mm_plan(None, None, None) == -1
+    assert lib.mm_plan_destroy(None) == 0
+
+
+def test_struct_layout_matches_header():
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "mm.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("mm_geometry %zu\n", sizeof(mm_geometry));
+  printf("mm_plan_info_t %zu\n", sizeof(mm_plan_info_t));
+  printf("mm_solve_opts %zu\n", sizeof(mm_solve_opts));
+  printf("mm_solve_info %zu\n", sizeof(mm_solve_info));
+  P(mm_geometry, n_pix_global) P(mm_geometry, band_coef) P(mm_geometry, cond_max)
+  P(mm_geometry, fft_size) P(mm_plan_info_t, lambda_max) P(mm_plan_info_t, n_chunks)
+  P(mm_solve_info, relres) P(mm_solve_info, ms) P(mm_solve_opts, use_graph)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
+                       check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    M = mapmaker
+    exp = {
+        "mm_geometry": ctypes.sizeof(M.Geometry), "mm_plan_info_t": ctypes.sizeof(M.PlanInfo),
+        "mm_solve_opts": ctypes.sizeof(M.SolveOpts), "mm_solve_info": ctypes.sizeof(M.SolveInfo),
+        "mm_geometry.n_pix_global": M.Geometry.n_pix_global.offset,
+        "mm_geometry.band_coef": M.Geometry.band_coef.offset,
+        "mm_geometry.cond_max": M.Geometry.cond_max.offset,
+        "mm_geometry.fft_size": M.Geometry.fft_size.offset,
+        "mm_plan_info_t.lambda_max": M.PlanInfo.lambda_max.offset,
+        "mm_plan_info_t.n_chunks": M.PlanInfo.n_chunks.offset,
+        "mm_solve_info.relres": M.SolveInfo.relres.offset,
+        "mm_solve_info.ms": M.SolveInfo.ms.offset,
+        "mm_solve_opts.use_graph": M.SolveOpts.use_graph.offset,
+    }
+    assert {k: int(v) for k, v in got.items()} == exp

@@ -1,0 +1,257 @@
+"""GPU parity: every step of the hot path, through the C ABI, against the FP64 oracle.
+
+Tolerances (derived from the arithmetic):
+  * integer work (hits, kept pixel ids, gap counts): bit-exact;
+  * P x: FP64 sums rounded once to FP32 -> within 1 FP32 ulp of the oracle rounded to FP32;
+  * P^T u: FP64 accumulation of identical FP32 products -> 1e-12 relative (summation order);
+  * M_BD r: FP64 3x3 products -> 1e-12 relative;
+  * N^-1 t: FP32 arithmetic; direct sums err ~ u32 * sum|c||t| and the FFT ~ u32 log2(N)
+    relative to ||u|| -> relative L2 <= 2e-6;
+  * A x and b: FP32 time-domain storage + FP32 Toeplitz -> relative L2 <= 3e-6;
+  * PCG maps: relative L2 <= 1e-6 against the oracle's FP64 map at the same tolerance 1e-8
+    (the FP32 floor measured with the oracle's single-precision emulation is ~1.3e-7).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _plan(lib, prob, **kw):
+    return lib.Plan.from_problem(prob, **kw)
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+CASES = {
+    "tiny": lambda: synth.make_config("tiny"),
+    "random_flags_gaps": lambda: synth.make_random_small(seed=3, n_samples=5003, n_pix=60,
+                                                         n_dets=4, lam_max=40, flag_frac=0.1,
+                                                         gap_frac=0.2, dwell=5),
+    "ground_mini": lambda: synth.make_ground(cfg_id=21, n_dets=6, samples_per_det=40000,
+                                             interval=9000, side=32, lam=700, flag_frac=0.02),
+    "ground_lam8192": lambda: synth.make_ground(cfg_id=22, n_dets=4, samples_per_det=1 << 17,
+                                                interval=1 << 16, side=48, lam=8192),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        prob = CASES[name]()
+        _cache[name] = (prob, O.plan_from_problem(prob))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_plan_pixels_and_hits_bit_exact(gpu_lib, name):
+    prob, ref = case(name)
+    plan = _plan(gpu_lib, prob)
+    ids, hits = plan.pixels()
+    assert np.array_equal(ids, ref.kept)
+    assert np.array_equal(hits, ref.hits)
+    info = plan.info
+    assert info["n_obs"] == ref.n_kept + ref.n_excised
+    assert info["n_excised"] == ref.n_excised
+    assert info["n_gap_samples"] == int(np.sum(ref.lpix < 0))
+
+
+@pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini"])
+def test_unpoint_within_one_ulp(gpu_lib, name):
+    prob, ref = case(name)
+    plan = _plan(gpu_lib, prob)
+    x = np.random.default_rng(1).standard_normal((ref.n_kept, 3))
+    t = plan.unpoint(_dev(x)).cpu().numpy()
+    want = O.unpoint(ref, x).astype(np.float32)
+    ulp = np.spacing(np.abs(want).astype(np.float32))
+    assert np.all(np.abs(t - want) <= ulp)
+
+
+@pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini", "ground_lam8192"])
+def test_point_parity(gpu_lib, name):
+    prob, ref = case(name)
+    plan = _plan(gpu_lib, prob)
+    u = np.random.default_rng(2).standard_normal(ref.n_samples).astype(np.float32)
+    y = plan.point(_dev(u)).cpu().numpy()
+    want = O.point(ref, u.astype(np.float64))
+    scale = np.abs(want).max()
+    assert np.abs(y - want).max() <= 1e-12 * max(scale, 1.0)
+
+
+@pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini", "ground_lam8192"])
+@pytest.mark.parametrize("algo", ["auto", "direct", "fft"])
+def test_noise_weight_parity(gpu_lib, name, algo):
+    prob, ref = case(name)
+    if algo == "direct" and prob.lam_max > 4096:
+        pytest.skip("direct product limited to lambda <= 4096")
+    a = {"auto": gpu_lib.TOEPLITZ_AUTO, "direct": gpu_lib.TOEPLITZ_DIRECT,
+         "fft": gpu_lib.TOEPLITZ_FFT}[algo]
+    plan = _plan(gpu_lib, prob, toeplitz_algo=a)
+    t = np.random.default_rng(3).standard_normal(ref.n_samples).astype(np.float32)
+    u = plan.noise_weight(_dev(t)).cpu().numpy()
+    want = O.noise_weight(t.astype(np.float64), ref)
+    assert _rel(u, want) <= 2e-6
+    # samples outside every block pass through unchanged (bit-exact copy)
+    cov = np.zeros(ref.n_samples, bool)
+    for s, L in zip(ref.blk_start, ref.blk_len):
+        cov[s:s + L] = True
+    assert np.array_equal(u[~cov], t[~cov])
+
+
+@pytest.mark.parametrize("fft_size", [2048, 4096, 8192, 16384, 32768])
+def test_noise_weight_every_fft_size(gpu_lib, fft_size):
+    lam = min(900, fft_size // 2 - 1)
+    prob = synth.make_ground(cfg_id=23, n_dets=2, samples_per_det=50001, interval=20011,
+                             side=16, lam=lam)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=fft_size)
+    assert plan.info["fft_size"] == fft_size
+    t = np.random.default_rng(4).standard_normal(ref.n_samples).astype(np.float32)
+    u = plan.noise_weight(_dev(t)).cpu().numpy()
+    assert _rel(u, O.noise_weight(t.astype(np.float64), ref)) <= 2e-6
+
+
+@pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini"])
+def test_precond_parity(gpu_lib, name):
+    prob, ref = case(name)
+    plan = _plan(gpu_lib, prob)
+    r = np.random.default_rng(5).standard_normal((ref.n_kept, 3))
+    z = plan.precond_bj(_dev(r)).cpu().numpy()
+    want = O.precond_bj(ref, r)
+    assert np.abs(z - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_A_and_rhs_parity(gpu_lib, name):
+    prob, ref = case(name)
+    plan = _plan(gpu_lib, prob)
+    x = np.random.default_rng(6).standard_normal((ref.n_kept, 3))
+    y = plan.apply_A(_dev(x)).cpu().numpy()
+    assert _rel(y, O.apply_A(ref, x)) <= 3e-6
+    b = plan.rhs(_dev(prob.d[0])).cpu().numpy()
+    assert _rel(b, O.rhs(ref, prob.d[0])) <= 3e-6
+
+
+@pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini"])
+def test_pcg_map_parity(gpu_lib, name):
+    prob, ref = case(name)
+    plan = _plan(gpu_lib, prob)
+    x, info = plan.pcg_solve(_dev(prob.d[0]), tol=1e-8)
+    res = O.pcg(ref, O.rhs(ref, prob.d[0]), tol=1e-8)
+    m = x.cpu().numpy()
+    assert info["converged"] == 1 and res.converged
+    assert _rel(m, res.x) <= 1e-6
+    assert abs(info["iterations"] - res.iterations) <= 2
+    assert info["relres"] < 1e-8
+    assert info["true_relres"] < 1e-7
+
+
+def test_pcg_graph_and_eager_agree(gpu_lib):
+    prob, ref = case("tiny")
+    plan = _plan(gpu_lib, prob)
+    torch = _torch()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d = _dev(prob.d[0])
+        xg, ig = plan.pcg_solve(d, use_graph=True, stream=s)
+        xe, ie = plan.pcg_solve(d, use_graph=False, stream=s)
+        xg2, ig2 = plan.pcg_solve(d, use_graph=True, check_every=8, stream=s)
+    s.synchronize()
+    assert ig["iterations"] == ie["iterations"] == ig2["iterations"]
+    assert _rel(xg.cpu().numpy(), xe.cpu().numpy()) <= 1e-10
+    assert _rel(xg2.cpu().numpy(), xe.cpu().numpy()) <= 1e-10
+
+
+def test_white_noise_binned_map_in_one_iteration(gpu_lib):
+    prob = synth.make_raster(cfg_id=52, n_dets=3, side=16, dwell=4, lam=0, noise="white")
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob)
+    x, info = plan.pcg_solve(_dev(prob.d[0]))
+    assert info["iterations"] == 1
+    assert _rel(x.cpu().numpy(), O.binned_map(ref, prob.d[0])) <= 1e-7
+
+
+def test_noiseless_recovers_sky(gpu_lib):
+    prob = synth.make_raster(cfg_id=53, n_dets=4, side=32, dwell=8, lam=256, noise="none")
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob)
+    x, info = plan.pcg_solve(_dev(prob.d[0]), tol=1e-10)
+    assert _rel(x.cpu().numpy(), prob.m_true[0][ref.kept]) <= 1e-6
+
+
+def test_multiple_rhs_and_restart(gpu_lib):
+    prob = synth.make_raster(cfg_id=54, n_dets=2, side=16, dwell=8, lam=128, n_rhs=3)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob)
+    x, infos = plan.pcg_solve(_dev(prob.d))
+    for j in range(3):
+        want = O.pcg(ref, O.rhs(ref, prob.d[j])).x
+        assert _rel(x[j].cpu().numpy(), want) <= 1e-6
+    # restart from the solution: already converged, zero iterations
+    x0 = x[0].clone()
+    x1, info = plan.pcg_solve(_dev(prob.d[0]), x=x0, use_x0=True)
+    assert info["iterations"] <= 1
+    assert _rel(x1.cpu().numpy(), x[0].cpu().numpy()) <= 1e-7
+
+
+def test_zero_data_and_empty_edges(gpu_lib):
+    prob = synth.make_raster(cfg_id=55, n_dets=2, side=8, dwell=4, lam=16)
+    plan = _plan(gpu_lib, prob)
+    torch = _torch()
+    d0 = torch.zeros(prob.n_samples, dtype=torch.float32, device="cuda")
+    x, info = plan.pcg_solve(d0)
+    assert info["iterations"] == 0 and info["converged"] == 1
+    assert not torch.any(x)
+    # a geometry with no blocks: N^-1 = identity, every sample passes through
+    pix = _dev(prob.pix)
+    p2 = gpu_lib.Plan(pix, _dev(prob.wq), _dev(prob.wu), prob.n_pix_global, [], [], [], [])
+    t = torch.randn(prob.n_samples, device="cuda")
+    assert torch.equal(p2.noise_weight(t), t)
+    # every sample flagged: nothing observed, empty map, converged at once
+    allflag = torch.full((prob.n_samples,), -1, dtype=torch.int32, device="cuda")
+    p3 = gpu_lib.Plan(allflag, _dev(prob.wq), _dev(prob.wu), prob.n_pix_global,
+                      prob.blk_start, prob.blk_len, prob.blk_band, prob.bands)
+    assert p3.n_kept == 0
+    x3, info3 = p3.pcg_solve(_dev(prob.d[0]))
+    assert info3["iterations"] == 0
+
+
+def test_invalid_inputs_are_rejected(gpu_lib):
+    prob = synth.make_raster(cfg_id=56, n_dets=2, side=8, dwell=4, lam=16)
+    torch = _torch()
+    bad = prob.pix.copy()
+    bad[7] = prob.n_pix_global  # out of range
+    with pytest.raises(gpu_lib.MMError) as e:
+        gpu_lib.Plan(_dev(bad), _dev(prob.wq), _dev(prob.wu), prob.n_pix_global,
+                     prob.blk_start, prob.blk_len, prob.blk_band, prob.bands)
+    assert e.value.status == -1
+    with pytest.raises(gpu_lib.MMError) as e:  # overlapping blocks
+        gpu_lib.Plan(_dev(prob.pix), _dev(prob.wq), _dev(prob.wu), prob.n_pix_global,
+                     [0, 10], [20, 20], [0, 0], prob.bands)
+    assert e.value.status == -1
+    neg = [np.array([1.0, 0.9, 0.0], np.float32)]  # symbol 1 + 1.8 cos w < 0 at w = pi
+    with pytest.raises(gpu_lib.MMError) as e:
+        gpu_lib.Plan(_dev(prob.pix), _dev(prob.wq), _dev(prob.wu), prob.n_pix_global,
+                     [0], [prob.n_samples], [0], neg)
+    assert e.value.status == -2
+    del torch
