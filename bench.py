@@ -38,9 +38,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+KERNEL_SOURCES = {
+    "toeplitz": ("toeplitz.hip",),
+    "unpoint": ("pointing.hip",),
+    "point": ("pointing.hip", "wave_runs.h"),
+}
+
+
+def kernel_source_hash(kernel):
+    """Hash of the sources a kernel is built from (a PMC summary is only valid for them)."""
     h = hashlib.sha256()
-    for f in ("toeplitz.hip", "pointing.hip", "wave_runs.h", "cg.hip"):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, "paper_2112_03370_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -54,7 +62,7 @@ def committed_traffic(kernel, workload):
     txt = open(path).read()
     m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"HBM bytes per launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash(kernel):
         return None
     return float(m_bytes.group(1))
 
@@ -74,8 +82,9 @@ def cpu_baseline(prob, target_s=15.0):
     import oracle as O
     threads = len(os.sched_getaffinity(0))
     n_dets = len(prob.det_offset) - 1
-    per_det = int(prob.det_offset[1] - prob.det_offset[0])
-    use = max(1, min(n_dets, int(4_000_000 // per_det) or 1))
+    # enough detectors that pixels keep well-conditioned 3x3 blocks (one eighth of the focal
+    # plane, at least 4 detectors)
+    use = min(n_dets, max(4, n_dets // 8))
     s1 = int(prob.det_offset[use])
     sel = prob.blk_start + prob.blk_len <= s1
     plan = O.build_plan(prob.pix[:s1], prob.wq[:s1], prob.wu[:s1], prob.n_pix_global,

@@ -32,8 +32,24 @@ TimedLaunch::TimedLaunch(Plan* plan, int k, hipStream_t st) : P(plan), kind(k), 
 TimedLaunch::~TimedLaunch() {
   if (!e0) return;
   (void)hipEventRecord(e1, s);
-  P->timing.pending[kind].push_back(e0);
-  P->timing.pending[kind].push_back(e1);
+  P->timing.pending[kind].push_back(TimedPair{e0, e1, P->timing.tag});
+}
+
+void timing_drop_after(Plan* P, int32_t last) {
+  for (int k = 0; k < K_NKINDS; ++k) {
+    auto& v = P->timing.pending[k];
+    std::vector<TimedPair> keep;
+    for (const TimedPair& t : v) {
+      if (t.tag > last) {
+        (void)hipEventSynchronize(t.e1);
+        (void)hipEventDestroy(t.e0);
+        (void)hipEventDestroy(t.e1);
+      } else {
+        keep.push_back(t);
+      }
+    }
+    v.swap(keep);
+  }
 }
 
 }  // namespace mm
@@ -78,14 +94,14 @@ mm_status guarded(F&& f) {
 mm_status drain_timing(Plan* P) {
   for (int k = 0; k < K_NKINDS; ++k) {
     auto& v = P->timing.pending[k];
-    for (size_t i = 0; i + 1 < v.size(); i += 2) {
-      MM_HIP_TRY(hipEventSynchronize(v[i + 1]));
+    for (const TimedPair& t : v) {
+      MM_HIP_TRY(hipEventSynchronize(t.e1));
       float ms = 0.0f;
-      MM_HIP_TRY(hipEventElapsedTime(&ms, v[i], v[i + 1]));
+      MM_HIP_TRY(hipEventElapsedTime(&ms, t.e0, t.e1));
       P->timing.total_ms[k] += ms;
       P->timing.count[k] += 1;
-      (void)hipEventDestroy(v[i]);
-      (void)hipEventDestroy(v[i + 1]);
+      (void)hipEventDestroy(t.e0);
+      (void)hipEventDestroy(t.e1);
     }
     v.clear();
   }
@@ -181,11 +197,7 @@ mm_status mm_rhs(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d,
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
-    for (int32_t j = 0; j < k; ++j) {
-      MM_TRY(launch_mask_data(P, d + j * ld_d, P->t, s));
-      MM_TRY(launch_noise_weight(P, P->t, P->u, nullptr, s));
-      MM_TRY(launch_point(P, P->u, b + j * 3 * P->n_kept, true, nullptr, s));
-    }
+    for (int32_t j = 0; j < k; ++j) MM_TRY(compute_rhs(P, d + j * ld_d, b + j * 3 * P->n_kept, s));
     return MM_OK;
   });
 }

@@ -247,9 +247,13 @@ mm_status iteration(Plan* P, double* x, hipStream_t s) {
   const int32_t* done = &P->state->done;
   const int nrb = P->n_red_blocks;
   const int64_t nk = P->n_kept;
-  MM_TRY(launch_unpoint(P, P->p, P->t, done, s));
-  MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
-  MM_TRY(launch_point(P, P->u, P->q, false, done, s));
+  if (P->lambda_max == 0) {
+    MM_TRY(launch_diag_apply(P, P->p, nullptr, P->q, done, s));  // q was zeroed by k_update
+  } else {
+    MM_TRY(launch_unpoint(P, P->p, P->t, done, s));
+    MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
+    MM_TRY(launch_point(P, P->u, P->q, false, done, s));
+  }
   TimedLaunch tl(P, K_CG, s);
   hipLaunchKernelGGL(k_dot_pq, dim3(nrb), dim3(kThreads), 0, s, P->p, P->q, 3 * nk, P->partial,
                      P->state);
@@ -276,7 +280,21 @@ mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s) {
   return MM_OK;
 }
 
+mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s) {
+  if (P->lambda_max == 0) {
+    MM_TRY(launch_zero(b, 3 * P->n_kept, s));
+    return launch_diag_apply(P, nullptr, d, b, nullptr, s);
+  }
+  MM_TRY(launch_mask_data(P, d, P->t, s));
+  MM_TRY(launch_noise_weight(P, P->t, P->u, nullptr, s));
+  return launch_point(P, P->u, b, true, nullptr, s);
+}
+
 mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s) {
+  if (P->lambda_max == 0) {
+    MM_TRY(launch_zero(y, 3 * P->n_kept, s));
+    return launch_diag_apply(P, x, nullptr, y, done, s);
+  }
   MM_TRY(launch_unpoint(P, x, P->t, done, s));
   MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
   MM_TRY(launch_point(P, P->u, y, true, done, s));
@@ -284,9 +302,17 @@ mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipS
 }
 
 mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
-                    mm_solve_info* info, hipStream_t s) {
+                    mm_solve_info* info, hipStream_t caller) {
   mm_solve_opts opts{};
   if (o) opts = *o;
+  // The legacy null stream cannot be captured: replay graphs on a plan-owned stream that
+  // waits for the caller's prior work (the solve is synchronous, so no join is needed after).
+  hipStream_t s = caller;
+  if (caller == nullptr && opts.use_graph && !P->timing.enabled) {
+    if (P->aux == nullptr) MM_HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+    MM_HIP_TRY(hipStreamSynchronize(caller));
+    s = P->aux;
+  }
   const double tol = opts.tol > 0 ? opts.tol : 1e-8;
   const int max_iter = opts.max_iter > 0 ? opts.max_iter : 10000;
   const int nrb = P->n_red_blocks;
@@ -304,9 +330,8 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
   MM_HIP_TRY(hipEventRecord(ev0, s));
 
   // b = P^T N^-1 d
-  MM_TRY(launch_mask_data(P, d, P->t, s));
-  MM_TRY(launch_noise_weight(P, P->t, P->u, nullptr, s));
-  MM_TRY(launch_point(P, P->u, P->b, true, nullptr, s));
+  P->timing.tag = 0;
+  MM_TRY(compute_rhs(P, d, P->b, s));
   if (opts.use_x0) MM_TRY(apply_A(P, x, P->q, nullptr, s));
   hipLaunchKernelGGL(k_init, dim3(nrb), dim3(kThreads), 0, s, P->minv, P->b, P->q, P->r, P->z,
                      P->p, P->q, x, opts.use_x0 ? 1 : 0, nk, P->partial, nrb);
@@ -315,7 +340,9 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
   MM_HIP_TRY(hipGetLastError());
 
   // Iterate in chunks; the host reads the state between chunks.
-  int chunk = opts.check_every > 0 ? opts.check_every : 4;
+  // With per-kernel timing on, check after every iteration so that no launch is queued past
+  // convergence (every timed launch then does real work).
+  int chunk = P->timing.enabled ? 1 : (opts.check_every > 0 ? opts.check_every : 4);
   const bool use_graph = opts.use_graph && !P->timing.enabled;
   hipGraphExec_t gexec = nullptr;
   int graph_chunk = 0;
@@ -354,14 +381,19 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
       }
       MM_HIP_TRY(hipGraphLaunch(gexec, s));
     } else {
-      for (int i = 0; i < chunk; ++i) MM_TRY(iteration(P, x, s));
+      for (int i = 0; i < chunk; ++i) {
+        P->timing.tag = queued + i + 1;
+        MM_TRY(iteration(P, x, s));
+      }
+      P->timing.tag = 0;
     }
     queued += chunk;
-    if (opts.check_every <= 0 && chunk < 64) chunk *= 2;
+    if (opts.check_every <= 0 && !P->timing.enabled && chunk < 16) chunk *= 2;
   }
 
   // True residual with one more product.
   const CgState st = *P->h_state;
+  if (P->timing.enabled) timing_drop_after(P, st.iter);
   double true_rr = 0.0;
   if (nk > 0 && st.bb > 0.0) {
     MM_TRY(apply_A(P, x, P->q, nullptr, s));

@@ -73,12 +73,19 @@ struct CgState {
 
 enum KernelKind { K_UNPOINT = 0, K_TOEPLITZ = 1, K_POINT = 2, K_CG = 3, K_NKINDS = 4 };
 
+struct TimedPair {
+  hipEvent_t e0, e1;
+  int32_t tag;  // PCG iteration the launch belongs to (0 = outside the loop)
+};
+
 struct Timing {
   bool enabled = false;
-  std::vector<hipEvent_t> pending[K_NKINDS];  // start/stop pairs
+  int32_t tag = 0;
+  std::vector<TimedPair> pending[K_NKINDS];
   double total_ms[K_NKINDS] = {0, 0, 0, 0};
   int64_t count[K_NKINDS] = {0, 0, 0, 0};
 };
+
 
 struct Plan {
   int device = 0;
@@ -112,6 +119,8 @@ struct Plan {
   float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
   float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
+  Tile* tiles = nullptr;        // <= 4096-sample tiles with their diagonal weight c_0
+  int32_t n_tiles = 0;
   int32_t n_chunks = 0;
   int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
   int32_t n_id_seg = 0;
@@ -129,10 +138,15 @@ struct Plan {
   int32_t n_red_blocks = 0;
   CgState* state = nullptr;
   CgState* h_state = nullptr;   // pinned host mirror
+  hipStream_t aux = nullptr;    // plan-owned stream for graph replay when the caller's is null
 
   Timing timing;
   std::mutex mu;
 };
+
+// Drop timed launches of PCG iterations beyond `last` (queued after convergence; they exit at
+// once and are not kernel work).
+void timing_drop_after(Plan* P, int32_t last);
 
 // Allocation helper tracking plan bytes.
 template <class T>
@@ -169,7 +183,13 @@ mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* 
 mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, const int32_t* done,
                        hipStream_t s);
 mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s);
+// Diagonal weights (lambda_max = 0): y = P^T diag(c_0) (P x or masked d), all in FP64.
+mm_status launch_diag_apply(Plan* P, const double* x, const float* d, double* y,
+                            const int32_t* done, hipStream_t s);
 mm_status launch_zero(double* y, int64_t n, hipStream_t s);
+
+// b = P^T N^-1 d (b overwritten).
+mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s);
 
 // A x -> y (y overwritten), done-gated.
 mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s);

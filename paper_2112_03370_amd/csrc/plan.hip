@@ -371,13 +371,17 @@ mm_status validate(const mm_geometry* g, std::vector<int>& order, int32_t& lambd
 void destroy_plan(Plan* P) {
   if (!P) return;
   void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
-                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->id_seg, P->t, P->u,
+                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->tiles, P->id_seg, P->t, P->u,
                   P->r, P->z, P->p, P->q, P->b, P->partial, P->state};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->h_state) (void)hipHostFree(P->h_state);
+  if (P->aux) (void)hipStreamDestroy(P->aux);
   for (int k = 0; k < K_NKINDS; ++k)
-    for (hipEvent_t e : P->timing.pending[k]) (void)hipEventDestroy(e);
+    for (const TimedPair& t : P->timing.pending[k]) {
+      (void)hipEventDestroy(t.e0);
+      (void)hipEventDestroy(t.e1);
+    }
   delete P;
 }
 
@@ -497,7 +501,6 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   Scratch<double> Bg;
   Scratch<int32_t> hits_g, local, counts, err;
   Scratch<uint8_t> keep;
-  Scratch<Tile> dtiles;
   Scratch<unsigned long long> ctr;  // [0] observed, [1] gap samples
   Scratch<int64_t> total;
   MM_TRY(Bg.alloc(6 * std::max<int64_t>(ng, 1)));
@@ -507,7 +510,8 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   MM_TRY(err.alloc(1));
   MM_TRY(ctr.alloc(2));
   MM_TRY(total.alloc(1));
-  MM_TRY(dtiles.alloc(tiles.size()));
+  MM_TRY(dalloc(P, &P->tiles, tiles.size()));
+  P->n_tiles = static_cast<int32_t>(tiles.size());
   const int n_scan = static_cast<int>((ng + kScanChunk - 1) / kScanChunk);
   MM_TRY(counts.alloc(n_scan + 1));
   MM_HIP_TRY(hipMemsetAsync(Bg.p, 0, sizeof(double) * 6 * std::max<int64_t>(ng, 1), s));
@@ -516,10 +520,10 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   MM_HIP_TRY(hipMemsetAsync(ctr.p, 0, 2 * sizeof(unsigned long long), s));
   MM_HIP_TRY(hipMemsetAsync(total.p, 0, sizeof(int64_t), s));
   if (!tiles.empty()) {
-    MM_HIP_TRY(hipMemcpyAsync(dtiles.p, tiles.data(), tiles.size() * sizeof(Tile),
+    MM_HIP_TRY(hipMemcpyAsync(P->tiles, tiles.data(), tiles.size() * sizeof(Tile),
                               hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_plan_accumulate, dim3(static_cast<unsigned>(tiles.size())), dim3(kThreads),
-                       0, s, g->pix, g->w_q, g->w_u, dtiles.p, ng, Bg.p, hits_g.p, err.p);
+                       0, s, g->pix, g->w_q, g->w_u, P->tiles, ng, Bg.p, hits_g.p, err.p);
     MM_HIP_TRY(hipGetLastError());
   }
   int32_t h_err = 0;

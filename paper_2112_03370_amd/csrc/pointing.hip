@@ -154,6 +154,52 @@ __global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ 
   }
 }
 
+// Diagonal weights: per tile of samples with one weight c_0, y += P^T (c_0 (P x)) or
+// y += P^T (c_0 d) with every product in FP64 (no FP32 time-domain intermediate).
+__global__ __launch_bounds__(kThreads) void k_diag_apply(const int32_t* __restrict__ lpix,
+                                                         const float* __restrict__ wq,
+                                                         const float* __restrict__ wu,
+                                                         const Tile* __restrict__ tiles,
+                                                         const double* __restrict__ x,
+                                                         const float* __restrict__ d,
+                                                         double* __restrict__ y,
+                                                         const int32_t* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const Tile tl = tiles[blockIdx.x];
+  const PointFlush flush{y};
+  const double c0 = tl.c0;
+  for (int off = 0; off < tl.len; off += kPerBlock) {
+    int key[4];
+    double v[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = off + threadIdx.x * kPerThread + j;
+      key[j] = -1;
+      v[j][0] = v[j][1] = v[j][2] = 0.0;
+      if (o < tl.len) {
+        const int64_t i = tl.start + o;
+        const int k = lpix[i];
+        if (k >= 0) {
+          const double q = wq[i], w = wu[i];
+          double tv;
+          if (x != nullptr) {
+            const double* m = x + 3 * static_cast<int64_t>(k);
+            tv = m[0] + q * m[1] + w * m[2];
+          } else {
+            tv = d[i];
+          }
+          tv *= c0;
+          key[j] = k;
+          v[j][0] = tv;
+          v[j][1] = q * tv;
+          v[j][2] = w * tv;
+        }
+      }
+    }
+    wave_merge_runs<3>(key, v, flush);
+  }
+}
+
 __global__ void k_zero(double* __restrict__ y, int64_t n) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -163,6 +209,16 @@ __global__ void k_zero(double* __restrict__ y, int64_t n) {
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
+
+mm_status launch_diag_apply(Plan* P, const double* x, const float* d, double* y,
+                            const int32_t* done, hipStream_t s) {
+  if (P->n_tiles == 0 || P->n_kept == 0) return MM_OK;
+  TimedLaunch tl(P, K_POINT, s);
+  hipLaunchKernelGGL(k_diag_apply, dim3(P->n_tiles), dim3(kThreads), 0, s, P->lpix, P->wq, P->wu,
+                     P->tiles, x, d, y, done);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
 
 mm_status launch_zero(double* y, int64_t n, hipStream_t s) {
   if (n <= 0) return MM_OK;
