@@ -39,7 +39,8 @@ def log(*a):
 
 
 KERNEL_SOURCES = {
-    "toeplitz": ("toeplitz.hip",),
+    "apply_fused": ("apply_fused.hip", "fft_lds.h", "wave_runs.h"),
+    "toeplitz": ("toeplitz.hip", "fft_lds.h"),
     "unpoint": ("pointing.hip",),
     "point": ("pointing.hip", "wave_runs.h"),
 }
@@ -114,6 +115,8 @@ def main():
     ap.add_argument("--config", default="ground", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unfused", action="store_true",
+                    help="three-kernel FFT path (gather / Toeplitz / scatter) instead of fused")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for PMC scaling)")
     args = ap.parse_args()
@@ -141,7 +144,8 @@ def main():
     def step(timing=False):
         with torch.cuda.stream(stream):
             plan = mm.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
-                           prob.blk_band, prob.bands, det_offset=prob.det_offset, stream=stream)
+                           prob.blk_band, prob.bands, det_offset=prob.det_offset,
+                           flags=mm.FLAG_UNFUSED if args.unfused else 0, stream=stream)
             if timing:
                 plan.set_timing(True)
             x, info = plan.pcg_solve(d, tol=args.tol, stream=stream)
@@ -176,11 +180,16 @@ def main():
     n_s = prob.n_samples
     tot = {k: sum(kt[k][0] for kt in kts) for k in range(4)}
     cnt = {k: sum(kt[k][1] for kt in kts) for k in range(4)}
-    names = {0: "unpoint", 1: "toeplitz", 2: "point", 3: "cg_vector"}
+    fused = (not args.unfused) and pinfo["toeplitz_algo"] == mm.TOEPLITZ_FFT
+    names = {0: "unpoint", 1: "apply_fused" if fused else "toeplitz", 2: "point", 3: "cg_vector"}
     dom = max(range(3), key=lambda k: tot[k])
     avg_ms = tot[dom] / max(1, cnt[dom])
-    # algorithmic bytes per sample of each time-domain kernel (one launch covers n_samples)
-    bytes_per_sample = {0: 4 + 8 + 4, 1: 4 + 4, 2: 4 + 8 + 4}[dom]
+    # algorithmic bytes per sample and launch (one launch covers n_samples): pointing is 12 B
+    # (pixel int32 + two FP32 weights); time-domain vectors 4 B each
+    if dom == 1 and fused:
+        bytes_per_sample = 12                 # pointing read once; t and u never leave LDS
+    else:
+        bytes_per_sample = {0: 12 + 4, 1: 4 + 4, 2: 12 + 4}[dom]
     algo_bytes = bytes_per_sample * n_s
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
     traffic = committed_traffic(names[dom], args.config)

@@ -68,6 +68,7 @@ typedef struct mm_server mm_server_t;
  *               block; <= 0 selects 1e3.  Pixels with fewer than 3 hits are excised too.
  *   toeplitz_algo  MM_TOEPLITZ_*; fft_size  real FFT length for the overlap-save product
  *               (power of two in [2^11, 2^15], > 2 lambda_max), 0 = automatic.
+ *   flags       MM_FLAG_* bits.
  * All pointers are read only during mm_plan and may be released afterwards.
  */
 typedef struct {
@@ -89,7 +90,12 @@ typedef struct {
   double cond_max;
   int32_t toeplitz_algo;
   int32_t fft_size;
+  int32_t flags;            /* MM_FLAG_* bits, 0 = defaults */
 } mm_geometry;
+
+/* mm_geometry.flags: MM_FLAG_UNFUSED keeps the FFT path's gather, Toeplitz product and scatter
+ * as three kernels with FP32 time-domain vectors in HBM (the fused kernel is the default). */
+enum { MM_FLAG_UNFUSED = 1 };
 
 typedef struct {
   int64_t n_samples;

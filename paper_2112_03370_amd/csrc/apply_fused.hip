@@ -1,0 +1,178 @@
+// Fused system product for the FFT path: one workgroup per overlap-save segment does
+//
+//   gather   t = P x (FP64 sums rounded to FP32) or t = d at kept samples, straight into LDS
+//   Toeplitz u = N^-1 t by the LDS real FFT (shift-and-overlap segment, Toeplitz package)
+//   scatter  y += P^T u for the segment's outputs, FP64, run-merged atomics
+//
+// so the time-domain vectors never go to HBM: per output sample the kernel reads the pointing
+// of its input window (12 B per window sample, the lambda halo included) and again for its
+// outputs, and issues the run-merged atomics.  Segments are independent, so while some
+// workgroups stream pointing data others run their transforms, overlapping memory and VALU
+// work across the chip.  Samples outside every block (identity rows of stbmm) are handled by
+// the diagonal kernel over identity tiles.
+#include "fft_lds.h"
+#include "mm_internal.h"
+#include "wave_runs.h"
+
+namespace mm {
+
+namespace {
+
+using namespace fft;
+
+struct AtomicFlush {
+  double* y;
+  __device__ void operator()(int key, const double (&v)[3]) const {
+    double* dst = y + 3 * static_cast<int64_t>(key);
+    unsafeAtomicAdd(dst + 0, v[0]);
+    unsafeAtomicAdd(dst + 1, v[1]);
+    unsafeAtomicAdd(dst + 2, v[2]);
+  }
+};
+
+template <bool kFromData>
+__device__ __forceinline__ float gather_one(int key, float q, float w, const double* __restrict__ x,
+                                            float dv) {
+  if (key < 0) return 0.0f;
+  if constexpr (kFromData) {
+    return dv;
+  } else {
+    const double* m = x + 3 * static_cast<int64_t>(key);
+    return static_cast<float>(m[0] + static_cast<double>(q) * m[1] + static_cast<double>(w) * m[2]);
+  }
+}
+
+template <int LOG, bool kFromData>
+__global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
+    const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
+    const double* __restrict__ x, const float* __restrict__ d, int d_vec, double* __restrict__ y,
+    const Chunk* __restrict__ chunks, const float* __restrict__ spec,
+    const float2* __restrict__ tw0g, const float2* __restrict__ tw1g, int lam,
+    const int32_t* __restrict__ done) {
+  using C = FftCfg<LOG>;
+  constexpr int NC = C::NC, N = C::N, T = C::T;
+  __shared__ float2 buf[C::LDS];
+  __shared__ float2 tw0[128];
+  __shared__ float2 tw1[N / 128];
+  if (done != nullptr && *done) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 128; i += T) tw0[i] = tw0g[i];
+  for (int i = tid; i < N / 128; i += T) tw1[i] = tw1g[i];
+
+  const Chunk c = chunks[blockIdx.x];
+  const int64_t in0 = c.out0 - lam;
+  const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
+
+  // ---- gather the N-sample window (zero outside the block) ---------------------------------
+  for (int n = tid * 4; n < N; n += T * 4) {
+    const int64_t g = in0 + n;
+    float v[4];
+    if (g >= b0 && g + 4 <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
+      const int4 k4 = *reinterpret_cast<const int4*>(lpix + g);
+      const float4 q4 = *reinterpret_cast<const float4*>(wq + g);
+      const float4 u4 = *reinterpret_cast<const float4*>(wu + g);
+      float4 d4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (kFromData) d4 = *reinterpret_cast<const float4*>(d + g);
+      v[0] = gather_one<kFromData>(k4.x, q4.x, u4.x, x, d4.x);
+      v[1] = gather_one<kFromData>(k4.y, q4.y, u4.y, x, d4.y);
+      v[2] = gather_one<kFromData>(k4.z, q4.z, u4.z, x, d4.z);
+      v[3] = gather_one<kFromData>(k4.w, q4.w, u4.w, x, d4.w);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t gj = g + j;
+        v[j] = 0.0f;
+        if (gj >= b0 && gj < b1)
+          v[j] = gather_one<kFromData>(lpix[gj], wq[gj], wu[gj], x, kFromData ? d[gj] : 0.0f);
+      }
+    }
+    // samples n..n+3 are complex points n/2, n/2+1 (n/2 even: adjacent after padding)
+    float2* dst = buf + pad(n >> 1);
+    dst[0] = make_float2(v[0], v[1]);
+    dst[1] = make_float2(v[2], v[3]);
+  }
+  __syncthreads();
+
+  // ---- Toeplitz product in LDS ----------------------------------------------------------------
+  fft_forward<LOG, T>(buf, tw0, tw1);
+  symbol_multiply<LOG, T>(buf, spec + static_cast<int64_t>(c.band) * (NC + 1), tw0, tw1);
+  fft_forward<LOG, T>(buf, tw0, tw1);
+
+  // ---- scatter the segment's outputs ----------------------------------------------------------
+  const AtomicFlush flush{y};
+  for (int base = 0; base < c.out_len; base += T * 4) {  // same trip count for every lane
+    const int i0 = base + tid * 4;
+    const int64_t o = c.out0 + i0;
+    int key[4] = {-1, -1, -1, -1};
+    double v[4][3];
+    if (i0 + 4 <= c.out_len && (o & 3) == 0) {
+      const int4 k4 = *reinterpret_cast<const int4*>(lpix + o);
+      const float4 q4 = *reinterpret_cast<const float4*>(wq + o);
+      const float4 w4 = *reinterpret_cast<const float4*>(wu + o);
+      key[0] = k4.x; key[1] = k4.y; key[2] = k4.z; key[3] = k4.w;
+      const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
+      const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double tv = real_out(buf, lam + i0 + j);
+        v[j][0] = tv;
+        v[j][1] = static_cast<double>(qq[j]) * tv;
+        v[j][2] = static_cast<double>(ww[j]) * tv;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[j][0] = v[j][1] = v[j][2] = 0.0;
+        if (i0 + j < c.out_len) {
+          const int64_t oj = o + j;
+          key[j] = lpix[oj];
+          const double tv = real_out(buf, lam + i0 + j);
+          v[j][0] = tv;
+          v[j][1] = static_cast<double>(wq[oj]) * tv;
+          v[j][2] = static_cast<double>(wu[oj]) * tv;
+        }
+      }
+    }
+    wave_merge_runs<3>(key, v, flush);
+  }
+}
+
+template <int LOG>
+mm_status launch(Plan* P, const double* x, const float* d, double* y, const int32_t* done,
+                 hipStream_t s) {
+  using C = FftCfg<LOG>;
+  const int d_vec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 ? 1 : 0;
+  if (d != nullptr) {
+    hipLaunchKernelGGL((k_apply_fused<LOG, true>), dim3(P->n_chunks), dim3(C::T), 0, s, P->lpix,
+                       P->wq, P->wu, x, d, d_vec, y, P->chunks, P->spec, P->tw0, P->tw1,
+                       P->lambda_max, done);
+  } else {
+    hipLaunchKernelGGL((k_apply_fused<LOG, false>), dim3(P->n_chunks), dim3(C::T), 0, s, P->lpix,
+                       P->wq, P->wu, x, d, d_vec, y, P->chunks, P->spec, P->tw0, P->tw1,
+                       P->lambda_max, done);
+  }
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace
+
+mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
+                             const int32_t* done, hipStream_t s) {
+  if (P->n_kept == 0) return MM_OK;
+  if (P->n_chunks > 0) {
+    TimedLaunch tl(P, K_TOEPLITZ, s);
+    switch (P->fft_n) {
+      case 1 << 11: MM_TRY(launch<10>(P, x, d, y, done, s)); break;
+      case 1 << 12: MM_TRY(launch<11>(P, x, d, y, done, s)); break;
+      case 1 << 13: MM_TRY(launch<12>(P, x, d, y, done, s)); break;
+      case 1 << 14: MM_TRY(launch<13>(P, x, d, y, done, s)); break;
+      case 1 << 15: MM_TRY(launch<14>(P, x, d, y, done, s)); break;
+      default: return fail(MM_ERR_UNSUPPORTED, "FFT size not supported");
+    }
+  }
+  if (P->n_id_tiles > 0) MM_TRY(launch_diag_tiles(P, P->id_tiles, P->n_id_tiles, x, d, y, done, s));
+  return MM_OK;
+}
+
+}  // namespace mm

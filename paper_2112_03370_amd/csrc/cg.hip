@@ -249,6 +249,8 @@ mm_status iteration(Plan* P, double* x, hipStream_t s) {
   const int64_t nk = P->n_kept;
   if (P->lambda_max == 0) {
     MM_TRY(launch_diag_apply(P, P->p, nullptr, P->q, done, s));  // q was zeroed by k_update
+  } else if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
+    MM_TRY(launch_apply_fused(P, P->p, nullptr, P->q, done, s));
   } else {
     MM_TRY(launch_unpoint(P, P->p, P->t, done, s));
     MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
@@ -285,6 +287,10 @@ mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
     return launch_diag_apply(P, nullptr, d, b, nullptr, s);
   }
+  if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
+    MM_TRY(launch_zero(b, 3 * P->n_kept, s));
+    return launch_apply_fused(P, nullptr, d, b, nullptr, s);
+  }
   MM_TRY(launch_mask_data(P, d, P->t, s));
   MM_TRY(launch_noise_weight(P, P->t, P->u, nullptr, s));
   return launch_point(P, P->u, b, true, nullptr, s);
@@ -294,6 +300,10 @@ mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipS
   if (P->lambda_max == 0) {
     MM_TRY(launch_zero(y, 3 * P->n_kept, s));
     return launch_diag_apply(P, x, nullptr, y, done, s);
+  }
+  if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
+    MM_TRY(launch_zero(y, 3 * P->n_kept, s));
+    return launch_apply_fused(P, x, nullptr, y, done, s);
   }
   MM_TRY(launch_unpoint(P, x, P->t, done, s));
   MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));

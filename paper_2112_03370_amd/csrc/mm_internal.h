@@ -121,6 +121,9 @@ struct Plan {
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
   Tile* tiles = nullptr;        // <= 4096-sample tiles with their diagonal weight c_0
   int32_t n_tiles = 0;
+  Tile* id_tiles = nullptr;     // the tiles of samples outside every block (weight 1)
+  int32_t n_id_tiles = 0;
+  bool fused = true;            // FFT path: gather + Toeplitz + scatter in one kernel
   int32_t n_chunks = 0;
   int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
   int32_t n_id_seg = 0;
@@ -183,9 +186,15 @@ mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* 
 mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, const int32_t* done,
                        hipStream_t s);
 mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s);
-// Diagonal weights (lambda_max = 0): y = P^T diag(c_0) (P x or masked d), all in FP64.
+// Diagonal weights (lambda_max = 0): y += P^T diag(c_0) (P x or masked d), all in FP64.
 mm_status launch_diag_apply(Plan* P, const double* x, const float* d, double* y,
                             const int32_t* done, hipStream_t s);
+// Same over an explicit tile list.
+mm_status launch_diag_tiles(Plan* P, const Tile* tiles, int32_t n_tiles, const double* x,
+                            const float* d, double* y, const int32_t* done, hipStream_t s);
+// FFT path, fused: y += P^T N^-1 (P x) (d == nullptr) or y += P^T N^-1 d (x == nullptr).
+mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
+                             const int32_t* done, hipStream_t s);
 mm_status launch_zero(double* y, int64_t n, hipStream_t s);
 
 // b = P^T N^-1 d (b overwritten).

@@ -371,7 +371,7 @@ mm_status validate(const mm_geometry* g, std::vector<int>& order, int32_t& lambd
 void destroy_plan(Plan* P) {
   if (!P) return;
   void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
-                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->tiles, P->id_seg, P->t, P->u,
+                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->tiles, P->id_tiles, P->id_seg, P->t, P->u,
                   P->r, P->z, P->p, P->q, P->b, P->partial, P->state};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -427,7 +427,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   const int64_t ng = g->n_pix_global;
 
   // ---- segment tables: blocks and identity gaps ------------------------------------------
-  std::vector<Tile> tiles;
+  std::vector<Tile> tiles, id_tiles;
   std::vector<int64_t> idseg;
   auto add_tiles = [&](int64_t s0, int64_t len, float c0) {
     for (int64_t o = 0; o < len; o += kTile)
@@ -435,6 +435,8 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   };
   auto add_identity = [&](int64_t s0, int64_t len) {
     add_tiles(s0, len, 1.0f);
+    for (int64_t o = 0; o < len; o += kTile)
+      id_tiles.push_back(Tile{s0 + o, static_cast<int32_t>(std::min<int64_t>(kTile, len - o)), 1.0f});
     for (int64_t o = 0; o < len; o += 65536) {
       idseg.push_back(s0 + o);
       idseg.push_back(std::min<int64_t>(65536, len - o));
@@ -475,6 +477,9 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   P->n_id_seg = static_cast<int32_t>(idseg.size() / 2);
   P->h_id_seg = idseg;
   MM_TRY(upload(P, &P->chunks, chunks));
+  MM_TRY(upload(P, &P->id_tiles, id_tiles));
+  P->n_id_tiles = static_cast<int32_t>(id_tiles.size());
+  P->fused = (g->flags & MM_FLAG_UNFUSED) == 0;
   MM_TRY(upload(P, &P->id_seg, idseg));
 
   // ---- bands -------------------------------------------------------------------------------

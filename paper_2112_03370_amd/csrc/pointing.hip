@@ -210,14 +210,19 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 }  // namespace
 
-mm_status launch_diag_apply(Plan* P, const double* x, const float* d, double* y,
-                            const int32_t* done, hipStream_t s) {
-  if (P->n_tiles == 0 || P->n_kept == 0) return MM_OK;
+mm_status launch_diag_tiles(Plan* P, const Tile* tiles, int32_t n_tiles, const double* x,
+                            const float* d, double* y, const int32_t* done, hipStream_t s) {
+  if (n_tiles == 0 || P->n_kept == 0) return MM_OK;
   TimedLaunch tl(P, K_POINT, s);
-  hipLaunchKernelGGL(k_diag_apply, dim3(P->n_tiles), dim3(kThreads), 0, s, P->lpix, P->wq, P->wu,
-                     P->tiles, x, d, y, done);
+  hipLaunchKernelGGL(k_diag_apply, dim3(n_tiles), dim3(kThreads), 0, s, P->lpix, P->wq, P->wu,
+                     tiles, x, d, y, done);
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
+}
+
+mm_status launch_diag_apply(Plan* P, const double* x, const float* d, double* y,
+                            const int32_t* done, hipStream_t s) {
+  return launch_diag_tiles(P, P->tiles, P->n_tiles, x, d, y, done, s);
 }
 
 mm_status launch_zero(double* y, int64_t n, hipStream_t s) {

@@ -24,6 +24,7 @@ STATUS = {
     -7: "MM_ERR_UNSUPPORTED", -8: "MM_ERR_NOT_FOUND",
 }
 TOEPLITZ_AUTO, TOEPLITZ_DIRECT, TOEPLITZ_FFT = 0, 1, 2
+FLAG_UNFUSED = 1
 KIND_UNPOINT, KIND_TOEPLITZ, KIND_POINT, KIND_CG = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -42,7 +43,7 @@ class Geometry(ctypes.Structure):
         ("n_pix_global", _c_i64), ("n_blocks", _c_i32), ("blk_start", _vp), ("blk_len", _vp),
         ("blk_band", _vp), ("n_bands", _c_i32), ("band_ncoef", _vp), ("band_offset", _vp),
         ("band_coef", _vp), ("n_dets", _c_i32), ("det_offset", _vp), ("cond_max", _c_dbl),
-        ("toeplitz_algo", _c_i32), ("fft_size", _c_i32),
+        ("toeplitz_algo", _c_i32), ("fft_size", _c_i32), ("flags", _c_i32),
     ]
 
 
@@ -133,7 +134,7 @@ class Plan:
 
     def __init__(self, pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
                  det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0,
-                 stream=None):
+                 flags=0, stream=None):
         import torch
         lib = load()
         self._lib = lib
@@ -173,6 +174,7 @@ class Plan:
         g.cond_max = float(cond_max)
         g.toeplitz_algo = int(toeplitz_algo)
         g.fft_size = int(fft_size)
+        g.flags = int(flags)
         h = _vp()
         self._h = None
         check(lib.mm_plan(ctypes.byref(g), _stream(stream), ctypes.byref(h)))

@@ -48,7 +48,8 @@ int main(void) {
   printf("mm_solve_opts %zu\n", sizeof(mm_solve_opts));
   printf("mm_solve_info %zu\n", sizeof(mm_solve_info));
   P(mm_geometry, n_pix_global) P(mm_geometry, band_coef) P(mm_geometry, cond_max)
-  P(mm_geometry, fft_size) P(mm_plan_info_t, lambda_max) P(mm_plan_info_t, n_chunks)
+  P(mm_geometry, fft_size) P(mm_geometry, flags) P(mm_plan_info_t, lambda_max)
+  P(mm_plan_info_t, n_chunks)
   P(mm_solve_info, relres) P(mm_solve_info, ms) P(mm_solve_opts, use_graph)
   return 0;
 }
@@ -69,6 +70,7 @@ int main(void) {
         "mm_geometry.band_coef": M.Geometry.band_coef.offset,
         "mm_geometry.cond_max": M.Geometry.cond_max.offset,
         "mm_geometry.fft_size": M.Geometry.fft_size.offset,
+        "mm_geometry.flags": M.Geometry.flags.offset,
         "mm_plan_info_t.lambda_max": M.PlanInfo.lambda_max.offset,
         "mm_plan_info_t.n_chunks": M.PlanInfo.n_chunks.offset,
         "mm_solve_info.relres": M.SolveInfo.relres.offset,

@@ -142,9 +142,14 @@ def test_precond_parity(gpu_lib, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_apply_A_and_rhs_parity(gpu_lib, name):
+@pytest.mark.parametrize("mode", ["auto", "fft_fused", "fft_unfused"])
+def test_apply_A_and_rhs_parity(gpu_lib, name, mode):
     prob, ref = case(name)
-    plan = _plan(gpu_lib, prob)
+    kw = {}
+    if mode != "auto":
+        kw = dict(toeplitz_algo=gpu_lib.TOEPLITZ_FFT,
+                  flags=gpu_lib.FLAG_UNFUSED if mode == "fft_unfused" else 0)
+    plan = _plan(gpu_lib, prob, **kw)
     x = np.random.default_rng(6).standard_normal((ref.n_kept, 3))
     y = plan.apply_A(_dev(x)).cpu().numpy()
     assert _rel(y, O.apply_A(ref, x)) <= 3e-6
@@ -153,9 +158,10 @@ def test_apply_A_and_rhs_parity(gpu_lib, name):
 
 
 @pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini"])
-def test_pcg_map_parity(gpu_lib, name):
+@pytest.mark.parametrize("unfused", [False, True])
+def test_pcg_map_parity(gpu_lib, name, unfused):
     prob, ref = case(name)
-    plan = _plan(gpu_lib, prob)
+    plan = _plan(gpu_lib, prob, flags=gpu_lib.FLAG_UNFUSED if unfused else 0)
     x, info = plan.pcg_solve(_dev(prob.d[0]), tol=1e-8)
     res = O.pcg(ref, O.rhs(ref, prob.d[0]), tol=1e-8)
     m = x.cpu().numpy()
