@@ -171,6 +171,14 @@ __device__ __forceinline__ void fft_forward(float2* buf, const float2* tw0, cons
   if constexpr (REM == 1) fft_pass<NC, T, 2>(buf, p, tw0, tw1);
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn: give each XCD a contiguous run of segments
+// so neighbouring segments of a block (which share their lambda halos) meet in the same L2.
+__device__ __forceinline__ int xcd_ordered(int bid, int nblocks) {
+  const int x = bid & 7, r = bid >> 3;
+  const int per = nblocks >> 3, extra = nblocks & 7;
+  return x * per + (x < extra ? x : extra) + r;
+}
+
 template <int LOG>
 struct FftCfg {
   static constexpr int NC = 1 << LOG;   // complex points

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_toeplitz_fft(
   for (int i = tid; i < 128; i += T) tw0[i] = tw0g[i];
   for (int i = tid; i < N / 128; i += T) tw1[i] = tw1g[i];
 
-  const Chunk c = chunks[blockIdx.x];
+  const Chunk c = chunks[xcd_ordered(blockIdx.x, gridDim.x)];
   const int64_t in0 = c.out0 - lam;
   const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
   float* fbuf = reinterpret_cast<float*>(buf);
