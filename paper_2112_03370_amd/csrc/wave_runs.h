@@ -1,8 +1,8 @@
 // Wavefront merge of equal-key runs for scatter-adds (P^T and the block-Jacobi build).
 //
-// Each lane holds 4 consecutive samples with their keys (pixel ids, -1 = skip) and NV FP64
-// values.  Time-ordered data visit a pixel for several consecutive samples, so keys come in
-// runs.  The lane first sums the pieces of its own runs; runs strictly inside the lane are
+// Each lane holds SPL consecutive samples (lane l + 1 continues lane l) with their keys (pixel
+// ids, -1 = skip) and NV FP64 values.  Time-ordered data visit a pixel for several consecutive
+// samples, so keys come in runs.  The lane first sums the pieces of its own runs; runs strictly inside the lane are
 // flushed at once.  The run that ends the lane (its tail) may continue in the next lanes: an
 // inclusive segmented scan over the lane tails (a new segment starts where the key changes or
 // where a lane holds more than one run) gives every lane the sum of its chain so far.  The lane
@@ -15,9 +15,9 @@
 
 namespace mm {
 
-template <int NV, class Flush>
-__device__ __forceinline__ void wave_merge_runs(const int (&key)[4], const double (&v)[4][NV],
-                                                const Flush& flush) {
+template <int SPL, int NV, class Flush>
+__device__ __forceinline__ void wave_merge_runs_n(const int (&key)[SPL], const double (&v)[SPL][NV],
+                                                  const Flush& flush) {
   const int lane = static_cast<int>(threadIdx.x & 63u);
 
   // ---- runs inside the lane --------------------------------------------------------------
@@ -32,7 +32,7 @@ __device__ __forceinline__ void wave_merge_runs(const int (&key)[4], const doubl
   int hk = -1;
   bool single = true;
 #pragma unroll
-  for (int j = 1; j < 4; ++j) {
+  for (int j = 1; j < SPL; ++j) {
     if (key[j] != cur) {
       if (single) {
         hk = cur;
@@ -93,6 +93,12 @@ __device__ __forceinline__ void wave_merge_runs(const int (&key)[4], const doubl
     const bool consumed = (lane < 63) && !next_single && next_hk == tk;
     if (!consumed) flush(tk, S);
   }
+}
+
+template <int NV, class Flush>
+__device__ __forceinline__ void wave_merge_runs(const int (&key)[4], const double (&v)[4][NV],
+                                                const Flush& flush) {
+  wave_merge_runs_n<4, NV>(key, v, flush);
 }
 
 }  // namespace mm

@@ -133,6 +133,23 @@ def test_noise_weight_every_fft_size(gpu_lib, fft_size):
     assert err <= 2e-6, err
 
 
+@pytest.mark.parametrize("fft_size", [2048, 4096, 8192, 16384, 32768])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_apply_A_every_fft_size(gpu_lib, fft_size, flags):
+    # odd lambda and odd interval lengths: unaligned windows, ragged last segments
+    lam = min(901, fft_size // 2 - 1)
+    prob = synth.make_ground(cfg_id=24, n_dets=2, samples_per_det=50001, interval=20011,
+                             side=16, lam=lam, flag_frac=0.01)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=fft_size,
+                 flags=flags)
+    x = np.random.default_rng(7).standard_normal((ref.n_kept, 3))
+    err = float(_rel(plan.apply_A(_dev(x)).cpu().numpy(), O.apply_A(ref, x)))
+    assert err <= 3e-6, err
+    err = float(_rel(plan.rhs(_dev(prob.d[0])).cpu().numpy(), O.rhs(ref, prob.d[0])))
+    assert err <= 3e-6, err
+
+
 @pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini"])
 def test_precond_parity(gpu_lib, name):
     prob, ref = case(name)
@@ -149,8 +166,8 @@ def test_apply_A_and_rhs_parity(gpu_lib, name, mode):
     prob, ref = case(name)
     kw = {}
     if mode != "auto":
-        kw = dict(toeplitz_algo=gpu_lib.TOEPLITZ_FFT,
-                  flags=gpu_lib.FLAG_UNFUSED if mode == "fft_unfused" else 0)
+        flags = {"fft_fused": 0, "fft_unfused": gpu_lib.FLAG_UNFUSED}[mode]
+        kw = dict(toeplitz_algo=gpu_lib.TOEPLITZ_FFT, flags=flags)
     plan = _plan(gpu_lib, prob, **kw)
     x = np.random.default_rng(6).standard_normal((ref.n_kept, 3))
     y = plan.apply_A(_dev(x)).cpu().numpy()
