@@ -67,7 +67,9 @@ typedef struct mm_server mm_server_t;
  *   cond_max    excision threshold on the 2-norm condition number of each pixel's 3x3 BJ
  *               block; <= 0 selects 1e3.  Pixels with fewer than 3 hits are excised too.
  *   toeplitz_algo  MM_TOEPLITZ_*; fft_size  real FFT length for the overlap-save product
- *               (power of two in [2^11, 2^15], > 2 lambda_max), 0 = automatic.
+ *               (power of two in [2^11, 2^17], > 2 lambda_max), 0 = automatic.  Lengths up
+ *               to 2^15 run in one CU's LDS (fused with the pointing products); 2^16 and 2^17
+ *               (lambda up to 2^15) use a four-step transform through a device tile.
  *   flags       MM_FLAG_* bits.
  * All pointers are read only during mm_plan and may be released afterwards.
  */

@@ -119,6 +119,7 @@ struct Plan {
   float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
   float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
+  float2* scratch = nullptr;    // long segments: one NC-point complex tile per segment
   Tile* tiles = nullptr;        // <= 4096-sample tiles with their diagonal weight c_0
   int32_t n_tiles = 0;
   Tile* id_tiles = nullptr;     // the tiles of samples outside every block (weight 1)
@@ -215,5 +216,10 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
 int32_t choose_fft_size(int32_t lambda_max);
 bool fft_size_supported(int32_t n);
 int32_t max_direct_lambda();
+// Long segments (toeplitz_long.hip): N = 2^16, 2^17 through a global tile per segment.
+bool long_fft_size(int32_t n);
+int32_t long_fine_size();
+mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, const int32_t* done,
+                               hipStream_t s);
 
 }  // namespace mm

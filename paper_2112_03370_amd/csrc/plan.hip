@@ -248,13 +248,10 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
     const float* __restrict__ coef, const int64_t* __restrict__ off,
     const int32_t* __restrict__ ncoef, int M, int fft_n, float* __restrict__ spec,
     double* __restrict__ block_min) {
-  extern __shared__ float cs[];
   __shared__ double red[kThreads / 64];
   const int band = blockIdx.y;
   const int nc = ncoef[band];
-  const float* c = coef + off[band];
-  for (int i = threadIdx.x; i < nc; i += kThreads) cs[i] = c[i];
-  __syncthreads();
+  const float* cs = coef + off[band];  // every lane reads the same coefficient: broadcast loads
   const int k = blockIdx.x * kThreads + threadIdx.x;
   double f = INFINITY;
   if (k <= M / 2) {
@@ -371,7 +368,7 @@ mm_status validate(const mm_geometry* g, std::vector<int>& order, int32_t& lambd
 void destroy_plan(Plan* P) {
   if (!P) return;
   void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
-                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->tiles, P->id_tiles, P->id_seg, P->t, P->u,
+                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->scratch, P->tiles, P->id_tiles, P->id_seg, P->t, P->u,
                   P->r, P->z, P->p, P->q, P->b, P->partial, P->state};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -579,11 +576,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     const int gx = (M / 2 + 1 + kThreads - 1) / kThreads;
     Scratch<double> mins;
     MM_TRY(mins.alloc(static_cast<size_t>(gx) * g->n_bands));
-    int max_nc = 1;
-    for (int b = 0; b < g->n_bands; ++b) max_nc = std::max(max_nc, g->band_ncoef[b]);
-    const size_t lds = sizeof(float) * max_nc;
-    if (lds > 64 * 1024) return fail(MM_ERR_UNSUPPORTED, "band too long for the symbol kernel");
-    hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), lds, s, P->band_coef,
+    hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
                        P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
     MM_HIP_TRY(hipGetLastError());
     std::vector<double> h_mins(static_cast<size_t>(gx) * g->n_bands);
@@ -599,14 +592,17 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     }
   }
   if (algo == MM_TOEPLITZ_FFT) {
-    std::vector<float2> t0(128), t1(fft_n / 128);
+    // exp(-2 pi i m / fft_n) = coarse[m / F] * fine[m % F]; F = 128 (LDS kernels) or 512
+    // (four-step kernel)
+    const int F = long_fft_size(fft_n) ? long_fine_size() : 128;
+    std::vector<float2> t0(F), t1(fft_n / F);
     const double two_pi = 6.283185307179586476925286766559;
-    for (int m = 0; m < 128; ++m) {
+    for (int m = 0; m < F; ++m) {
       const double a = -two_pi * m / fft_n;
       t0[m] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
     }
-    for (int m = 0; m < fft_n / 128; ++m) {
-      const double a = -two_pi * (128.0 * m) / fft_n;
+    for (int m = 0; m < fft_n / F; ++m) {
+      const double a = -two_pi * (static_cast<double>(F) * m) / fft_n;
       t1[m] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
     }
     MM_TRY(upload(P, &P->tw0, t0));
@@ -614,6 +610,10 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   }
 
   // ---- workspace -----------------------------------------------------------------------------
+  if (algo == MM_TOEPLITZ_FFT && long_fft_size(fft_n)) {
+    P->fused = false;  // long segments: gather, four-step product and scatter as three kernels
+    MM_TRY(dalloc(P, &P->scratch, static_cast<size_t>(P->n_chunks) * (fft_n / 2)));
+  }
   MM_TRY(dalloc(P, &P->t, n));
   MM_TRY(dalloc(P, &P->u, n));
   const int64_t nu = 3 * n_kept;

@@ -115,15 +115,21 @@ mm_status launch_fft(Plan* P, const float* t, float* u, const int32_t* done, hip
 int32_t max_direct_lambda() { return kDirectMaxLambda; }
 
 bool fft_size_supported(int32_t n) {
-  return n == (1 << 11) || n == (1 << 12) || n == (1 << 13) || n == (1 << 14) || n == (1 << 15);
+  return n == (1 << 11) || n == (1 << 12) || n == (1 << 13) || n == (1 << 14) ||
+         n == (1 << 15) || long_fft_size(n);
 }
 
 int32_t choose_fft_size(int32_t lambda_max) {
-  // Smallest supported power of two with at least half of every segment being output.
-  int32_t n = 1 << 11;
-  while (n < 4 * lambda_max && n < (1 << 15)) n *= 2;
-  if (n <= 2 * lambda_max) return 0;
-  return n;
+  // Smallest power of two >= 4 lambda (at least half of every segment is output).  Up to 2^15
+  // the segment fits one CU's LDS; bands a little longer still use 2^15 while at least 8,192
+  // outputs per segment remain; longer bands go to the four-step kernel (up to 2^17).
+  int64_t n = 1 << 11;
+  while (n < 4 * static_cast<int64_t>(lambda_max)) n *= 2;
+  if (n <= (1 << 15)) return static_cast<int32_t>(n);
+  if ((1 << 15) - 2 * static_cast<int64_t>(lambda_max) >= 8192) return 1 << 15;
+  if (n <= (1 << 17)) return static_cast<int32_t>(n);
+  if ((1 << 17) - 2 * static_cast<int64_t>(lambda_max) >= 16384) return 1 << 17;
+  return 0;
 }
 
 mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* done,
@@ -131,7 +137,9 @@ mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* 
   if (P->n_samples == 0) return MM_OK;
   TimedLaunch tl(P, K_TOEPLITZ, s);
   if (P->n_chunks > 0) {
-    if (P->algo == MM_TOEPLITZ_FFT) {
+    if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n)) {
+      MM_TRY(launch_toeplitz_long(P, t, u, done, s));
+    } else if (P->algo == MM_TOEPLITZ_FFT) {
       switch (P->fft_n) {
         case 1 << 11: MM_TRY(launch_fft<10>(P, t, u, done, s)); break;
         case 1 << 12: MM_TRY(launch_fft<11>(P, t, u, done, s)); break;

@@ -293,3 +293,36 @@ def test_invalid_inputs_are_rejected(gpu_lib):
                      [0], [prob.n_samples], [0], neg)
     assert e.value.status == -2
     del torch
+
+
+# ------------------------------------------------------------------------------------------
+# Long bands: four-step segments of 2^16 and 2^17 samples
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lam,fft_size", [(12001, 65536), (20000, 131072), (32768, 0)])
+def test_noise_weight_long_band(gpu_lib, lam, fft_size):
+    prob = synth.make_ground(cfg_id=25, n_dets=2, samples_per_det=300001, interval=200003,
+                             side=16, lam=lam)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=fft_size)
+    assert plan.info["fft_size"] == (fft_size or 131072)
+    t = np.random.default_rng(8).standard_normal(ref.n_samples).astype(np.float32)
+    u = plan.noise_weight(_dev(t)).cpu().numpy()
+    err = float(_rel(u, O.noise_weight(t.astype(np.float64), ref)))
+    assert err <= 2e-6, err
+    x = np.random.default_rng(9).standard_normal((ref.n_kept, 3))
+    err = float(_rel(plan.apply_A(_dev(x)).cpu().numpy(), O.apply_A(ref, x)))
+    assert err <= 3e-6, err
+
+
+def test_satellite_long_band_pcg(gpu_lib):
+    prob = synth.make_satellite(cfg_id=26, n_dets=2, samples_per_det=1 << 18, interval=1 << 17,
+                                n_rings=32, n_phi=64, lam=1 << 14, fknee=0.05, fsample=20.0)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob)
+    assert plan.info["fft_size"] == 65536
+    x, info = plan.pcg_solve(_dev(prob.d[0]), tol=1e-8)
+    res = O.pcg(ref, O.rhs(ref, prob.d[0]), tol=1e-8)
+    err = float(_rel(x.cpu().numpy(), res.x))
+    assert info["converged"] == 1 and err <= 1e-6, (err, info, res.iterations)
+    assert abs(info["iterations"] - res.iterations) <= 2
