@@ -31,6 +31,8 @@ WORKLOADS = {
     "ground": "ground-like: 256 det x 2^20 samples (268,435,456), intervals 2^16, 512x512 patch, "
               "lambda 8192, f_knee U[0.1,2] Hz",
     "tiny": "tiny raster: 4 det x 65,536 samples, 64x64 patch, lambda 1024, f_knee 1 Hz",
+    "satellite": "satellite-like: 32 det x 2^23 samples (268,435,456), intervals 2^20, 786,432 "
+                 "pixels, HWP, lambda 32768, f_knee 0.05 Hz",
 }
 
 
@@ -74,6 +76,8 @@ def make_workload(name):
         return synth.make_config("ground")
     if name == "tiny":
         return synth.make_config("tiny")
+    if name == "satellite":
+        return synth.make_config("satellite")
     raise SystemExit(f"unknown workload {name}")
 
 

@@ -340,7 +340,8 @@ def make_satellite(cfg_id=2, n_dets=32, samples_per_det=1 << 23, interval=1 << 2
     wu = np.empty(n_s, np.float32)
     a = np.deg2rad(prec_angle_deg)
     year = samples_per_det / fsample
-    for det in range(n_dets):
+
+    def one(det):
         b = np.deg2rad(spin_angle_deg) + dbeta[det]
         for s0 in range(0, samples_per_det, chunk):
             s1 = min(samples_per_det, s0 + chunk)
@@ -350,11 +351,12 @@ def make_satellite(cfg_id=2, n_dets=32, samples_per_det=1 << 23, interval=1 << 2
             th_spin = 2.0 * np.pi * t / spin_period_s + dphase[det]
             # boresight in the spin frame, then tilt by the precession angle, then rotate with
             # the precession phase about the anti-sun axis (x), then the anti-sun axis about z
-            v = np.stack([np.cos(b) * np.ones_like(t), np.sin(b) * np.cos(th_spin),
-                          np.sin(b) * np.sin(th_spin)], axis=-1)
-            x1 = np.cos(a) * v[:, 0] - np.sin(a) * v[:, 1]
-            y1 = np.sin(a) * v[:, 0] + np.cos(a) * v[:, 1]
-            z1 = v[:, 2]
+            v0 = np.cos(b)
+            v1 = np.sin(b) * np.cos(th_spin)
+            v2 = np.sin(b) * np.sin(th_spin)
+            x1 = np.cos(a) * v0 - np.sin(a) * v1
+            y1 = np.sin(a) * v0 + np.cos(a) * v1
+            z1 = v2
             cp, sp = np.cos(th_prec), np.sin(th_prec)
             y2 = cp * y1 - sp * z1
             z2 = sp * y1 + cp * z1
@@ -365,6 +367,13 @@ def make_satellite(cfg_id=2, n_dets=32, samples_per_det=1 << 23, interval=1 << 2
             ang = 2.0 * psi_det[det] + 4.0 * (2.0 * np.pi * hwp_hz) * t
             wq[sl] = np.cos(ang)
             wu[sl] = np.sin(ang)
+
+    if n_dets == 1:
+        one(0)
+    else:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=_workers()) as ex:
+            list(ex.map(one, range(n_dets)))
     fknees = np.full(n_dets, fknee if noise == "1/f" else 0.0)
     bands = _bands_for(lam, fsample, sigma, fknees, alpha, noise)
     blk = _blocks_for(det_offset, interval, list(range(n_dets)))
