@@ -120,6 +120,9 @@ typedef struct {
   int32_t use_x0;         /* nonzero: start from the x passed in (restart); else x0 = 0 */
   int32_t check_every;    /* iterations between host convergence checks; <= 0 automatic */
   int32_t use_graph;      /* nonzero: replay iterations from a captured HIP graph */
+  int32_t block;          /* right-hand sides solved together (Alg. 2 on stacked columns):
+                             0 or 1 each column alone (Alg. 1); 2..32 that many at a time;
+                             < 0 tune among 8, 16, 32 on the first column groups */
 } mm_solve_opts;
 
 typedef struct {
@@ -128,7 +131,8 @@ typedef struct {
   double relres;          /* recursive ||r_k|| / ||b|| */
   double true_relres;     /* ||b - A x_k|| / ||b|| with one more product, FP64 reductions */
   double bnorm;           /* ||b||_2 */
-  double ms;              /* wall time of the solve on the stream (hipEvent) */
+  double ms;              /* wall time of the solve (of the column's group when block >= 2) */
+  int32_t block;          /* columns solved together with this one (1: alone) */
 } mm_solve_info;
 
 /* mm_plan -- build the device plan: copy the pointing to the device plan, count hits, build
@@ -179,10 +183,16 @@ mm_status mm_apply_A(const mm_plan_t* plan, const double* x, double* y, int32_t 
 mm_status mm_precond_bj(const mm_plan_t* plan, const double* r, double* z, int32_t k,
                         void* stream);
 
-/* Solve A x = P^T N^-1 d by PCG (Alg. 1) for k right-hand sides (each column independently).
- * d as in mm_rhs; x DEVICE double [k][n_kept][3] (read when opts->use_x0); info HOST array of
- * k entries (may be NULL).  opts may be NULL (defaults).  Synchronous: returns when x holds
- * the maps.  Errors: MM_ERR_NO_CONV (x = last iterate), MM_ERR_NOT_SPD, MM_ERR_HIP. */
+/* Solve A x = P^T N^-1 d for k right-hand sides.  opts->block 0/1: PCG (Alg. 1) on each
+ * column alone.  opts->block >= 2 (or < 0, tuned): columns are taken in groups of t and each
+ * group is solved by the enlarged-CG recurrences (Alg. 2, Orthomin form, search block
+ * Z = M_BD R with one column per right-hand side, t x t systems by an FP64 eigen
+ * pseudo-inverse, a column leaves the block once ||r_j|| < tol ||b_j||); one multi-column
+ * product per iteration serves the whole group; use_x0, use_graph and check_every do not
+ * apply (x starts at 0).  d as in mm_rhs; x DEVICE double [k][n_kept][3] (read when
+ * opts->use_x0); info HOST array of k entries (may be NULL).  opts may be NULL (defaults).
+ * Synchronous: returns when x holds the maps.  Errors: MM_ERR_NO_CONV (x = last iterate),
+ * MM_ERR_NOT_SPD, MM_ERR_OOM (block workspace: 4 t n_kept 3 doubles), MM_ERR_HIP. */
 mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d,
                        double* x, const mm_solve_opts* opts, mm_solve_info* info,
                        void* stream);

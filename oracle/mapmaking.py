@@ -35,7 +35,7 @@ __all__ = [
     "noise_weight_fft", "noise_weight", "unpoint", "point", "rhs", "apply_A", "precond_bj",
     "PCGResult", "pcg", "lanczos_extremes", "binned_map", "dense_pointing",
     "dense_noise_inverse", "dense_A", "solve_dense", "default_fft_size", "block_pcg",
-    "BlockPCGResult",
+    "BlockPCGResult", "block_ecg", "sym_pinv",
 ]
 
 DEFAULT_COND_MAX = 1.0e3
@@ -436,15 +436,16 @@ def solve_dense(plan, b):
 
 
 # --------------------------------------------------------------------------------------------
-# Block PCG over several right-hand sides sharing P and N^-1
+# Several right-hand sides sharing P and N^-1
 # --------------------------------------------------------------------------------------------
 
 @dataclasses.dataclass
 class BlockPCGResult:
     x: np.ndarray            # [k, n_kept, 3]
-    iterations: np.ndarray   # per column
+    iterations: np.ndarray   # per column: iteration at which the column met the stop test
     relres: np.ndarray
     converged: np.ndarray
+    block_iterations: int = 0
 
 
 def block_pcg(plan, B, tol=1e-8, max_iter=10000):
@@ -458,4 +459,63 @@ def block_pcg(plan, B, tol=1e-8, max_iter=10000):
     for j in range(k):
         res = pcg(plan, B[j], tol=tol, max_iter=max_iter)
         X[j], it[j], rr[j], cv[j] = res.x, res.iterations, res.relres, res.converged
-    return BlockPCGResult(X, it, rr, cv)
+    return BlockPCGResult(X, it, rr, cv, int(it.max()) if k else 0)
+
+
+def sym_pinv(G, rtol=1e-12):
+    """Pseudo-inverse of a symmetric positive semi-definite matrix by its eigen-decomposition,
+    dropping directions with eigenvalue below rtol * largest (rank-revealing safeguard)."""
+    w, V = np.linalg.eigh(G)
+    keep = w > rtol * max(w.max(), 0.0) if w.size else w > 0
+    inv = np.zeros_like(w)
+    inv[keep] = 1.0 / w[keep]
+    return (V * inv) @ V.T
+
+
+def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=1e-12):
+    """Enlarged-CG recurrences (Alg. 2, Orthomin variant) on t stacked right-hand sides.
+
+    R_0 = B (X_0 = 0), Z_1 = M R_0; per iteration with W = A Z_k and G = Z_k^T W:
+    P_k = Z_k G^{-1/2}, alpha = P_k^T R, X += P_k alpha, R -= A P_k alpha, then
+    Z_{k+1} = (I - P_k P_k^T A) M R.  Folding G^{-1/2} G^{-1/2} = G^{-1} the updates read
+    X += Z G^-1 (Z^T R), R -= W G^-1 (Z^T R), Z <- M R - Z G^-1 (W^T M R).  G^-1 is the
+    eigen-based pseudo-inverse (rank drop below rtol * largest eigenvalue) -- a safeguard the
+    paper's Cholesky square root lacks.  A column stops (its X frozen and it leaves the block)
+    when ||R_j|| < eps ||B_j||: the per-column stop test of Alg. 1 applied to stacked systems.
+    With t = 1 the recurrences are those of Alg. 1."""
+    A = apply or (lambda v: apply_A(plan, v))
+    M = precond or (lambda v: precond_bj(plan, v))
+    B = np.asarray(B, np.float64)
+    t = B.shape[0]
+    shape = B.shape[1:]
+    Bf = B.reshape(t, -1)
+    X = np.zeros_like(Bf)
+    R = Bf.copy()
+    nb = np.linalg.norm(Bf, axis=1)
+    iters = np.zeros(t, np.int64)
+    conv = nb == 0.0
+    active = np.flatnonzero(~conv)
+    Z = np.stack([M(R[j].reshape(shape)).reshape(-1) for j in active]) if active.size else R[:0]
+    k = 0
+    while active.size and k < max_iter:
+        W = np.stack([A(Z[i].reshape(shape)).reshape(-1) for i in range(Z.shape[0])])
+        G = Z @ W.T
+        Gi = sym_pinv(G, rtol)
+        a1 = Gi @ (Z @ R[active].T)                      # [z, active]
+        X[active] += (Z.T @ a1).T
+        R[active] -= (W.T @ a1).T
+        k += 1
+        rel = np.linalg.norm(R[active], axis=1) / nb[active]
+        done = rel < tol
+        iters[active] = k
+        conv[active[done]] = True
+        keep = ~done
+        if not keep.any():
+            active = active[keep]
+            break
+        MR = np.stack([M(R[j].reshape(shape)).reshape(-1) for j in active[keep]])
+        a2 = Gi @ (W @ MR.T)
+        Z = MR - (Z.T @ a2).T
+        active = active[keep]
+    relres = np.where(nb > 0, np.linalg.norm(R, axis=1) / np.where(nb > 0, nb, 1.0), 0.0)
+    return BlockPCGResult(X.reshape(B.shape), iters, relres, conv, k)

@@ -212,9 +212,7 @@ mm_status mm_apply_A(const mm_plan_t* plan, const double* x, double* y, int32_t 
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
-    for (int32_t j = 0; j < k; ++j)
-      MM_TRY(apply_A(P, x + j * 3 * P->n_kept, y + j * 3 * P->n_kept, nullptr, s));
-    return MM_OK;
+    return apply_A_multi(P, x, 3 * P->n_kept, y, 3 * P->n_kept, k, s);
   });
 }
 
@@ -245,6 +243,10 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
+    if (opts && opts->block != 0 && opts->block != 1 && k > 0) {
+      if (opts->use_x0) return fail(MM_ERR_INVALID, "use_x0 is not supported with block != 0/1");
+      return block_solve(P, d, k, ld_d, x, opts, info, s);
+    }
     mm_status worst = MM_OK;
     std::string msg;
     for (int32_t j = 0; j < k; ++j) {

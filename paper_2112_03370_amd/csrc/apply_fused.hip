@@ -45,8 +45,9 @@ __device__ __forceinline__ float gather_one(int key, float q, float w, const dou
 template <int LOG, bool kFromData>
 __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
-    const double* __restrict__ x, const float* __restrict__ d, int d_vec, double* __restrict__ y,
-    const Chunk* __restrict__ chunks, const float* __restrict__ spec,
+    const double* __restrict__ x0, const float* __restrict__ d0, int d_vec, double* __restrict__ y0,
+    int ncol, int64_t ldx, int64_t ldy, const Chunk* __restrict__ chunks,
+    const float* __restrict__ spec,
     const float2* __restrict__ tw0g, const float2* __restrict__ tw1g, int lam,
     const int32_t* __restrict__ done) {
   using C = FftCfg<LOG>;
@@ -59,7 +60,14 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
   for (int i = tid; i < 128; i += T) tw0[i] = tw0g[i];
   for (int i = tid; i < N / 128; i += T) tw1[i] = tw1g[i];
 
-  const Chunk c = chunks[xcd_ordered(blockIdx.x, gridDim.x)];
+  // workgroup -> (segment, column), columns fastest: an XCD runs all columns of a segment
+  // back to back, so the pointing re-reads of the later columns hit its L2
+  const int wg = xcd_ordered(blockIdx.x, gridDim.x);
+  const int col = wg % ncol;
+  const Chunk c = chunks[wg / ncol];
+  const double* __restrict__ x = kFromData ? x0 : x0 + col * ldx;
+  const float* __restrict__ d = kFromData ? d0 + col * ldx : d0;
+  double* __restrict__ y = y0 + col * ldy;
   const int64_t in0 = c.out0 - lam;
   const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
 
@@ -138,18 +146,21 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
 }
 
 template <int LOG>
-mm_status launch(Plan* P, const double* x, const float* d, double* y, const int32_t* done,
-                 hipStream_t s) {
+mm_status launch(Plan* P, const double* x, const float* d, int64_t ldx, double* y, int64_t ldy,
+                 int ncol, const int32_t* done, hipStream_t s) {
   using C = FftCfg<LOG>;
-  const int d_vec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 ? 1 : 0;
+  const bool vec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 && (ldx & 3) == 0;
+  const int d_vec = vec ? 1 : 0;
+  const int64_t grid = static_cast<int64_t>(P->n_chunks) * ncol;
+  if (grid > INT32_MAX) return fail(MM_ERR_UNSUPPORTED, "too many segment x column workgroups");
   if (d != nullptr) {
-    hipLaunchKernelGGL((k_apply_fused<LOG, true>), dim3(P->n_chunks), dim3(C::T), 0, s, P->lpix,
-                       P->wq, P->wu, x, d, d_vec, y, P->chunks, P->spec, P->tw0, P->tw1,
-                       P->lambda_max, done);
+    hipLaunchKernelGGL((k_apply_fused<LOG, true>), dim3(static_cast<unsigned>(grid)), dim3(C::T), 0,
+                       s, P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks,
+                       P->spec, P->tw0, P->tw1, P->lambda_max, done);
   } else {
-    hipLaunchKernelGGL((k_apply_fused<LOG, false>), dim3(P->n_chunks), dim3(C::T), 0, s, P->lpix,
-                       P->wq, P->wu, x, d, d_vec, y, P->chunks, P->spec, P->tw0, P->tw1,
-                       P->lambda_max, done);
+    hipLaunchKernelGGL((k_apply_fused<LOG, false>), dim3(static_cast<unsigned>(grid)), dim3(C::T), 0,
+                       s, P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks,
+                       P->spec, P->tw0, P->tw1, P->lambda_max, done);
   }
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
@@ -158,20 +169,27 @@ mm_status launch(Plan* P, const double* x, const float* d, double* y, const int3
 }  // namespace
 
 mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
-                             const int32_t* done, hipStream_t s) {
-  if (P->n_kept == 0) return MM_OK;
+                             const int32_t* done, hipStream_t s, int32_t ncol, int64_t ldx,
+                             int64_t ldy) {
+  if (P->n_kept == 0 || ncol <= 0) return MM_OK;
+  if (ldx == 0) ldx = d != nullptr ? P->n_samples : 3 * P->n_kept;
+  if (ldy == 0) ldy = 3 * P->n_kept;
   if (P->n_chunks > 0) {
     TimedLaunch tl(P, K_TOEPLITZ, s);
     switch (P->fft_n) {
-      case 1 << 11: MM_TRY(launch<10>(P, x, d, y, done, s)); break;
-      case 1 << 12: MM_TRY(launch<11>(P, x, d, y, done, s)); break;
-      case 1 << 13: MM_TRY(launch<12>(P, x, d, y, done, s)); break;
-      case 1 << 14: MM_TRY(launch<13>(P, x, d, y, done, s)); break;
-      case 1 << 15: MM_TRY(launch<14>(P, x, d, y, done, s)); break;
+      case 1 << 11: MM_TRY(launch<10>(P, x, d, ldx, y, ldy, ncol, done, s)); break;
+      case 1 << 12: MM_TRY(launch<11>(P, x, d, ldx, y, ldy, ncol, done, s)); break;
+      case 1 << 13: MM_TRY(launch<12>(P, x, d, ldx, y, ldy, ncol, done, s)); break;
+      case 1 << 14: MM_TRY(launch<13>(P, x, d, ldx, y, ldy, ncol, done, s)); break;
+      case 1 << 15: MM_TRY(launch<14>(P, x, d, ldx, y, ldy, ncol, done, s)); break;
       default: return fail(MM_ERR_UNSUPPORTED, "FFT size not supported");
     }
   }
-  if (P->n_id_tiles > 0) MM_TRY(launch_diag_tiles(P, P->id_tiles, P->n_id_tiles, x, d, y, done, s));
+  if (P->n_id_tiles > 0) {
+    for (int32_t j = 0; j < ncol; ++j)
+      MM_TRY(launch_diag_tiles(P, P->id_tiles, P->n_id_tiles, d ? nullptr : x + j * ldx,
+                               d ? d + j * ldx : nullptr, y + j * ldy, done, s));
+  }
   return MM_OK;
 }
 

@@ -1,0 +1,528 @@
+// Stacked right-hand sides solved together by the enlarged-CG recurrences (Alg. 2, Orthomin
+// variant) applied to t right-hand sides that share P and N^-1:
+//
+//   R = B, Z = M R;  repeat:  W = A Z (one multi-column product), G = Z^T W, H1 = Z^T R,
+//   X += Z G^+ H1,  R -= W G^+ H1,  stop columns with ||R_j|| < eps ||B_j||,
+//   Z <- M R - Z G^+ (W^T M R)
+//
+// (P_k = Z G^-1/2 folds into G^+ = G^-1/2 G^-1/2).  G^+ is an FP64 eigen pseudo-inverse that
+// drops directions below 1e-12 of the largest eigenvalue, a safeguard against the rank loss of
+// the search block (the paper's Cholesky square root has none).  Converged columns leave the
+// block (their X is final).  The t x t algebra runs on the host in FP64; the tall-skinny Gram
+// products, updates and the block-Jacobi apply run in the kernels below, in FP64.
+//
+// Block size: opts->block >= 2 fixes t; opts->block < 0 tunes it: the first column groups are
+// solved with t = 8, 16, 32 in turn (real work, not a rehearsal), the block size with the
+// lowest time per right-hand side then solves the remaining columns.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxT = 32;
+constexpr int kTileRows = 64;
+
+// partial[wg][i * tv + j] = sum over the workgroup's rows of U_i[r] V_j[r]
+__global__ __launch_bounds__(kThreads) void k_gram(const double* __restrict__ U, int tu,
+                                                   int64_t ldu, const double* __restrict__ V,
+                                                   int tv, int64_t ldv, int64_t n,
+                                                   double* __restrict__ partial) {
+  __shared__ double su[kMaxT][kTileRows + 1];
+  __shared__ double sv[kMaxT][kTileRows + 1];
+  const int npair = tu * tv;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * kTileRows; r0 < n;
+       r0 += static_cast<int64_t>(gridDim.x) * kTileRows) {
+    for (int e = threadIdx.x; e < kMaxT * kTileRows; e += kThreads) {
+      const int col = e / kTileRows, row = e % kTileRows;
+      const int64_t r = r0 + row;
+      su[col][row] = (col < tu && r < n) ? U[col * ldu + r] : 0.0;
+      sv[col][row] = (col < tv && r < n) ? V[col * ldv + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int pidx = threadIdx.x + q * kThreads;
+      if (pidx < npair) {
+        const int i = pidx / tv, j = pidx % tv;
+        double s = 0.0;
+        for (int row = 0; row < kTileRows; ++row) s += su[i][row] * sv[j][row];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int pidx = threadIdx.x + q * kThreads;
+    if (pidx < npair) partial[static_cast<int64_t>(blockIdx.x) * npair + pidx] = acc[q];
+  }
+}
+
+// out[e] = sum_w partial[w][e], fixed order
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ partial,
+                                                          int nwg, int count,
+                                                          double* __restrict__ out) {
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  if (e >= count) return;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += partial[static_cast<int64_t>(w) * count + e];
+  out[e] = s;
+}
+
+// X_cols[j] += sum_i Z_i a1[i][j];  R_j -= sum_i W_i a1[i][j];  rr partial of ||R_j||^2
+template <int TM>
+__global__ __launch_bounds__(kThreads) void k_block_update(
+    const double* __restrict__ Z, const double* __restrict__ W, int tz, double* __restrict__ R,
+    int ta, int64_t nu, double* __restrict__ x, const int32_t* __restrict__ cols,
+    const double* __restrict__ a1, double* __restrict__ rr_partial) {
+  __shared__ double sa[kMaxT * kMaxT];
+  __shared__ double red[kThreads / 64][TM];
+  for (int e = threadIdx.x; e < tz * ta; e += kThreads) sa[e] = a1[e];
+  __syncthreads();
+  double rr[TM];
+#pragma unroll
+  for (int j = 0; j < TM; ++j) rr[j] = 0.0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; r < nu;
+       r += static_cast<int64_t>(gridDim.x) * kThreads) {
+    double z[TM], w[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      z[i] = i < tz ? Z[i * nu + r] : 0.0;
+      w[i] = i < tz ? W[i * nu + r] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
+      if (j < ta) {
+        double dx = 0.0, dr = 0.0;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          if (i < tz) {
+            dx += z[i] * sa[i * ta + j];
+            dr += w[i] * sa[i * ta + j];
+          }
+        }
+        double* xc = x + static_cast<int64_t>(cols[j]) * nu;
+        xc[r] += dx;
+        const double rn = R[j * nu + r] - dr;
+        R[j * nu + r] = rn;
+        rr[j] += rn * rn;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    double v = rr[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if (lane == 0) red[wv][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < ta) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) s += red[q][threadIdx.x];
+    rr_partial[static_cast<int64_t>(blockIdx.x) * ta + threadIdx.x] = s;
+  }
+}
+
+// Z_j <- MR_j - sum_i Z_i a2[i][j]  for j < tn (in place: each row reads all old Z first)
+template <int TM>
+__global__ __launch_bounds__(kThreads) void k_block_direction(double* __restrict__ Z, int tz,
+                                                              const double* __restrict__ MR,
+                                                              int tn, int64_t nu,
+                                                              const double* __restrict__ a2) {
+  __shared__ double sa[kMaxT * kMaxT];
+  for (int e = threadIdx.x; e < tz * tn; e += kThreads) sa[e] = a2[e];
+  __syncthreads();
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; r < nu;
+       r += static_cast<int64_t>(gridDim.x) * kThreads) {
+    double z[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) z[i] = i < tz ? Z[i * nu + r] : 0.0;
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
+      if (j < tn) {
+        double s = MR[j * nu + r];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          if (i < tz) s -= z[i] * sa[i * tn + j];
+        Z[j * nu + r] = s;
+      }
+    }
+  }
+}
+
+// rr_partial[wg][j] = partial sum of (B_j - Y_j)^2 (or B_j^2 when Y is null)
+template <int TM>
+__global__ __launch_bounds__(kThreads) void k_col_norms(const double* __restrict__ B, int t,
+                                                        const double* __restrict__ Y, int64_t nu,
+                                                        double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64][TM];
+  double acc[TM];
+#pragma unroll
+  for (int j = 0; j < TM; ++j) acc[j] = 0.0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; r < nu;
+       r += static_cast<int64_t>(gridDim.x) * kThreads) {
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
+      if (j < t) {
+        const double v = B[j * nu + r] - (Y ? Y[j * nu + r] : 0.0);
+        acc[j] += v * v;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    double v = acc[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if (lane == 0) red[wv][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < t) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) s += red[q][threadIdx.x];
+    partial[static_cast<int64_t>(blockIdx.x) * t + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_zero_cols(double* __restrict__ x, const int32_t* __restrict__ cols, int t,
+                            int64_t nu) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < t * nu;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int j = static_cast<int>(e / nu);
+    x[static_cast<int64_t>(cols[j]) * nu + (e % nu)] = 0.0;
+  }
+}
+
+#define MM_TM_DISPATCH(KERNEL, t, grid, s, ...)                                             \
+  do {                                                                                      \
+    if ((t) <= 8)                                                                           \
+      hipLaunchKernelGGL(KERNEL<8>, dim3(grid), dim3(kThreads), 0, s, __VA_ARGS__);         \
+    else if ((t) <= 16)                                                                     \
+      hipLaunchKernelGGL(KERNEL<16>, dim3(grid), dim3(kThreads), 0, s, __VA_ARGS__);        \
+    else                                                                                    \
+      hipLaunchKernelGGL(KERNEL<32>, dim3(grid), dim3(kThreads), 0, s, __VA_ARGS__);        \
+  } while (0)
+
+// ---- host-side t x t algebra (FP64) ---------------------------------------------------------
+
+// Pseudo-inverse of a symmetric positive semi-definite n x n matrix (row-major) by cyclic
+// Jacobi eigen-decomposition; eigenvalues below rtol * largest are dropped.
+void sym_pinv(const std::vector<double>& G, int n, double rtol, std::vector<double>& out) {
+  std::vector<double> a(G), v(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a[i * n + j] * a[i * n + j];
+        if (i != j) off += a[i * n + j] * a[i * n + j];
+      }
+    if (off <= 1e-30 * tot || tot == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // eigenvectors
+          const double vkp = v[k * n + p], vkq = v[k * n + q];
+          v[k * n + p] = c * vkp - s * vkq;
+          v[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double wmax = 0.0;
+  for (int i = 0; i < n; ++i) wmax = std::max(wmax, a[i * n + i]);
+  out.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int e = 0; e < n; ++e) {
+    const double w = a[e * n + e];
+    if (!(w > rtol * wmax) || w <= 0.0) continue;
+    const double inv = 1.0 / w;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) out[i * n + j] += v[i * n + e] * inv * v[j * n + e];
+  }
+}
+
+// C (n x m) = A (n x n) B (n x m), row-major
+void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, int m,
+            std::vector<double>& C) {
+  C.assign(static_cast<size_t>(n) * m, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double aik = A[i * n + k];
+      for (int j = 0; j < m; ++j) C[i * m + j] += aik * B[k * m + j];
+    }
+}
+
+struct BlockWs {
+  double* R = nullptr;
+  double* Z = nullptr;
+  double* W = nullptr;
+  double* MR = nullptr;
+  double* small = nullptr;    // t x t matrices
+  double* partial = nullptr;  // Gram / norm partials
+  int32_t* cols = nullptr;
+  int cap = 0;
+  int nwg = 0;
+};
+
+int gram_grid(int64_t nu) {
+  int64_t g = (nu + kTileRows - 1) / kTileRows;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 512)));
+}
+
+int rows_grid(int64_t nu) {
+  int64_t g = (nu + kThreads - 1) / kThreads;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 1024)));
+}
+
+mm_status ensure_ws(Plan* P, BlockWs& ws, int t) {
+  if (ws.cap >= t) return MM_OK;
+  const int64_t nu = 3 * P->n_kept;
+  for (void* p : {static_cast<void*>(ws.R), static_cast<void*>(ws.Z), static_cast<void*>(ws.W),
+                  static_cast<void*>(ws.MR), static_cast<void*>(ws.small),
+                  static_cast<void*>(ws.partial), static_cast<void*>(ws.cols)})
+    if (p) (void)hipFree(p);
+  ws = BlockWs{};
+  auto alloc = [&](void** p, size_t bytes) -> mm_status {
+    if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+      *p = nullptr;
+      return fail(MM_ERR_OOM, "hipMalloc (block workspace) failed");
+    }
+    return MM_OK;
+  };
+  const size_t vec = sizeof(double) * static_cast<size_t>(t) * nu;
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.R), vec));
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.Z), vec));
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.W), vec));
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.MR), vec));
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.small), sizeof(double) * 4 * kMaxT * kMaxT));
+  ws.nwg = std::max(gram_grid(nu), rows_grid(nu));
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.partial),
+               sizeof(double) * static_cast<size_t>(ws.nwg) * kMaxT * kMaxT));
+  MM_TRY(alloc(reinterpret_cast<void**>(&ws.cols), sizeof(int32_t) * kMaxT));
+  ws.cap = t;
+  return MM_OK;
+}
+
+void free_ws(BlockWs& ws) {
+  for (void* p : {static_cast<void*>(ws.R), static_cast<void*>(ws.Z), static_cast<void*>(ws.W),
+                  static_cast<void*>(ws.MR), static_cast<void*>(ws.small),
+                  static_cast<void*>(ws.partial), static_cast<void*>(ws.cols)})
+    if (p) (void)hipFree(p);
+  ws = BlockWs{};
+}
+
+// Gram U^T V (tu x tv, row-major) to the host.
+mm_status gram(const double* U, int tu, const double* V, int tv, int64_t nu, BlockWs& ws,
+               std::vector<double>& out, hipStream_t s) {
+  const int g = gram_grid(nu);
+  hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V, tv, nu, nu, ws.partial);
+  const int count = tu * tv;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     ws.partial, g, count, ws.small);
+  MM_HIP_TRY(hipGetLastError());
+  out.resize(count);
+  MM_HIP_TRY(hipMemcpyAsync(out.data(), ws.small, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
+// Per-column ||B_j - Y_j||^2 (Y may be null) to the host.
+mm_status col_norms(const double* B, const double* Y, int t, int64_t nu, BlockWs& ws,
+                    std::vector<double>& out, hipStream_t s) {
+  const int g = rows_grid(nu);
+  MM_TM_DISPATCH(k_col_norms, t, g, s, B, t, Y, nu, ws.partial);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(kThreads), 0, s, ws.partial, g, t, ws.small);
+  MM_HIP_TRY(hipGetLastError());
+  out.resize(t);
+  MM_HIP_TRY(hipMemcpyAsync(out.data(), ws.small, sizeof(double) * t, hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
+// Solve the columns `cols` (at most kMaxT) together.
+mm_status solve_group(Plan* P, const float* d, int64_t ld_d, double* x,
+                      const std::vector<int32_t>& cols, double tol, int max_iter,
+                      mm_solve_info* info, int block_used, BlockWs& ws, hipStream_t s) {
+  const int t = static_cast<int>(cols.size());
+  const int64_t nu = 3 * P->n_kept;
+  MM_TRY(ensure_ws(P, ws, t));
+  auto ev = std::chrono::steady_clock::now();
+
+  // R_j = b_j = P^T N^-1 d_j, X_j = 0
+  MM_HIP_TRY(hipMemcpyAsync(ws.cols, cols.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_zero_cols, dim3(rows_grid(t * nu)), dim3(kThreads), 0, s, x, ws.cols, t, nu);
+  for (int j = 0; j < t; ++j) MM_TRY(compute_rhs(P, d + cols[j] * ld_d, ws.R + j * nu, s));
+  std::vector<double> bb;
+  MM_TRY(col_norms(ws.R, nullptr, t, nu, ws, bb, s));
+  std::vector<double> bnorm(t);
+  for (int j = 0; j < t; ++j) bnorm[j] = std::sqrt(bb[j]);
+
+  // active slots: columns with b != 0 (others are solved by x = 0)
+  std::vector<int32_t> act;           // user column of each active slot
+  std::vector<int> slot_of;           // original position of each active slot
+  std::vector<int> iters(t, 0), conv(t, 0);
+  std::vector<double> relres(t, 0.0);
+  for (int j = 0; j < t; ++j) {
+    if (bnorm[j] > 0.0) {
+      if (static_cast<int>(act.size()) != j)
+        MM_HIP_TRY(hipMemcpyAsync(ws.R + act.size() * nu, ws.R + j * nu, sizeof(double) * nu,
+                                  hipMemcpyDeviceToDevice, s));
+      act.push_back(cols[j]);
+      slot_of.push_back(j);
+    } else {
+      conv[j] = 1;
+    }
+  }
+  int ta = static_cast<int>(act.size());
+  int tz = ta;
+  std::vector<double> G, H, Gi, A;
+  if (ta > 0) {
+    MM_TRY(launch_precond_multi(P, ws.R, ws.Z, ta, s));  // Z = M R
+  }
+  int k = 0;
+  while (ta > 0 && k < max_iter) {
+    MM_TRY(apply_A_multi(P, ws.Z, nu, ws.W, nu, tz, s));  // W = A Z
+    MM_TRY(gram(ws.Z, tz, ws.W, tz, nu, ws, G, s));       // G = Z^T W
+    MM_TRY(gram(ws.Z, tz, ws.R, ta, nu, ws, H, s));       // H1 = Z^T R
+    sym_pinv(G, tz, 1e-12, Gi);
+    matmul(Gi, H, tz, ta, A);                              // a1 = G^+ H1  (tz x ta)
+    MM_HIP_TRY(hipMemcpyAsync(ws.cols, act.data(), sizeof(int32_t) * ta, hipMemcpyHostToDevice, s));
+    MM_HIP_TRY(hipMemcpyAsync(ws.small + kMaxT * kMaxT, A.data(), sizeof(double) * A.size(),
+                              hipMemcpyHostToDevice, s));
+    const int g = rows_grid(nu);
+    MM_TM_DISPATCH(k_block_update, tz, g, s, ws.Z, ws.W, tz, ws.R, ta, nu, x, ws.cols,
+                   ws.small + kMaxT * kMaxT, ws.partial);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(kThreads), 0, s, ws.partial, g, ta, ws.small);
+    MM_HIP_TRY(hipGetLastError());
+    std::vector<double> rr(ta);
+    MM_HIP_TRY(hipMemcpyAsync(rr.data(), ws.small, sizeof(double) * ta, hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    ++k;
+    // stop test per column; compact R to the remaining columns
+    std::vector<int32_t> nact;
+    std::vector<int> nslot;
+    for (int i = 0; i < ta; ++i) {
+      const int j = slot_of[i];
+      const double rel = std::sqrt(std::max(rr[i], 0.0)) / bnorm[j];
+      relres[j] = rel;
+      iters[j] = k;
+      if (rel < tol) {
+        conv[j] = 1;
+      } else {
+        if (static_cast<int>(nact.size()) != i)
+          MM_HIP_TRY(hipMemcpyAsync(ws.R + nact.size() * nu, ws.R + i * nu, sizeof(double) * nu,
+                                    hipMemcpyDeviceToDevice, s));
+        nact.push_back(act[i]);
+        nslot.push_back(j);
+      }
+    }
+    const int tn = static_cast<int>(nact.size());
+    if (tn == 0) {
+      ta = 0;
+      break;
+    }
+    MM_TRY(launch_precond_multi(P, ws.R, ws.MR, tn, s));   // MR = M R
+    MM_TRY(gram(ws.W, tz, ws.MR, tn, nu, ws, H, s));       // H2 = W^T MR
+    matmul(Gi, H, tz, tn, A);                              // a2 = G^+ H2  (tz x tn)
+    MM_HIP_TRY(hipMemcpyAsync(ws.small + kMaxT * kMaxT, A.data(), sizeof(double) * A.size(),
+                              hipMemcpyHostToDevice, s));
+    MM_TM_DISPATCH(k_block_direction, tz, g, s, ws.Z, tz, ws.MR, tn, nu,
+                   ws.small + kMaxT * kMaxT);
+    MM_HIP_TRY(hipGetLastError());
+    act.swap(nact);
+    slot_of.swap(nslot);
+    ta = tz = tn;
+  }
+
+  // true residuals ||b - A x|| (W = A X, R = b)
+  std::vector<double> tr(t, 0.0);
+  MM_HIP_TRY(hipMemcpyAsync(ws.cols, cols.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+  for (int j = 0; j < t; ++j) {
+    MM_TRY(compute_rhs(P, d + cols[j] * ld_d, ws.R + j * nu, s));
+    MM_TRY(apply_A(P, x + static_cast<int64_t>(cols[j]) * nu, ws.W + j * nu, nullptr, s));
+  }
+  MM_TRY(col_norms(ws.R, ws.W, t, nu, ws, tr, s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ev).count();
+  for (int j = 0; j < t; ++j) {
+    mm_solve_info& in = info[cols[j]];
+    in.iterations = iters[j];
+    in.converged = conv[j];
+    in.relres = relres[j];
+    in.bnorm = bnorm[j];
+    in.true_relres = bnorm[j] > 0 ? std::sqrt(tr[j]) / bnorm[j] : 0.0;
+    in.ms = ms;
+    in.block = block_used;
+  }
+  return MM_OK;
+}
+
+}  // namespace
+
+mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* x,
+                      const mm_solve_opts* o, mm_solve_info* info, hipStream_t s) {
+  const double tol = o->tol > 0 ? o->tol : 1e-8;
+  const int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
+  std::vector<mm_solve_info> local(static_cast<size_t>(k));
+  mm_solve_info* inf = info ? info : local.data();
+  BlockWs ws;
+  struct Guard {
+    BlockWs& w;
+    ~Guard() { free_ws(w); }
+  } guard{ws};
+  std::vector<int> candidates;
+  if (o->block < 0) {
+    candidates = {8, 16, 32};
+  } else {
+    candidates = {std::min(std::max(2, static_cast<int>(o->block)), kMaxT)};
+  }
+  int32_t next = 0;
+  size_t ci = 0;
+  int best = candidates[0];
+  double best_cost = INFINITY;
+  while (next < k) {
+    const bool tuning = o->block < 0 && ci < candidates.size();
+    const int t = tuning ? candidates[ci] : best;
+    const int n = std::min<int32_t>(t, k - next);
+    std::vector<int32_t> cols(n);
+    std::iota(cols.begin(), cols.end(), next);
+    const auto t0 = std::chrono::steady_clock::now();
+    MM_TRY(solve_group(P, d, ld_d, x, cols, tol, max_iter, inf, t, ws, s));
+    const double cost = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / n;
+    if (tuning) {
+      if (n == t && cost < best_cost) {
+        best_cost = cost;
+        best = t;
+      }
+      ++ci;
+    }
+    next += n;
+  }
+  for (int j = 0; j < k; ++j) {
+    if (inf[j].converged != 1) return fail(MM_ERR_NO_CONV, "block solve reached max_iter");
+  }
+  return MM_OK;
+}
+
+}  // namespace mm

@@ -282,6 +282,19 @@ mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s) {
   return MM_OK;
 }
 
+mm_status launch_precond_multi(Plan* P, const double* r, double* z, int32_t ncol,
+                               hipStream_t s) {
+  // ncol contiguous columns of 3 n_kept values each (column j at offset 3 j n_kept).
+  const int64_t n = P->n_kept;
+  if (n == 0 || ncol <= 0) return MM_OK;
+  int64_t g = (n * ncol + kThreads - 1) / kThreads;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_precond, dim3(static_cast<unsigned>(g)), dim3(kThreads), 0, s, P->minv, r,
+                     z, n, n * ncol);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
 mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s) {
   if (P->lambda_max == 0) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
@@ -308,6 +321,17 @@ mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipS
   MM_TRY(launch_unpoint(P, x, P->t, done, s));
   MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
   MM_TRY(launch_point(P, P->u, y, true, done, s));
+  return MM_OK;
+}
+
+mm_status apply_A_multi(Plan* P, const double* x, int64_t ldx, double* y, int64_t ldy,
+                        int32_t ncol, hipStream_t s) {
+  if (ncol <= 0 || P->n_kept == 0) return MM_OK;
+  if (P->lambda_max != 0 && P->algo == MM_TOEPLITZ_FFT && P->fused) {
+    for (int32_t j = 0; j < ncol; ++j) MM_TRY(launch_zero(y + j * ldy, 3 * P->n_kept, s));
+    return launch_apply_fused(P, x, nullptr, y, nullptr, s, ncol, ldx, ldy);
+  }
+  for (int32_t j = 0; j < ncol; ++j) MM_TRY(apply_A(P, x + j * ldx, y + j * ldy, nullptr, s));
   return MM_OK;
 }
 
@@ -426,6 +450,7 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
     info->relres = st.bb > 0 ? std::sqrt(st.rr / st.bb) : 0.0;
     info->true_relres = st.bb > 0 ? std::sqrt(true_rr / st.bb) : 0.0;
     info->ms = ms;
+    info->block = 1;
   }
   if (st.done == 2) return fail(MM_ERR_NOT_SPD, "PCG breakdown: p^T A p <= 0 or r^T z <= 0");
   if (st.done != 1) return fail(MM_ERR_NO_CONV, "PCG reached max_iter without converging");

@@ -187,15 +187,19 @@ mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* 
 mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, const int32_t* done,
                        hipStream_t s);
 mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s);
+mm_status launch_precond_multi(Plan* P, const double* r, double* z, int32_t ncol,
+                               hipStream_t s);
 // Diagonal weights (lambda_max = 0): y += P^T diag(c_0) (P x or masked d), all in FP64.
 mm_status launch_diag_apply(Plan* P, const double* x, const float* d, double* y,
                             const int32_t* done, hipStream_t s);
 // Same over an explicit tile list.
 mm_status launch_diag_tiles(Plan* P, const Tile* tiles, int32_t n_tiles, const double* x,
                             const float* d, double* y, const int32_t* done, hipStream_t s);
-// FFT path, fused: y += P^T N^-1 (P x) (d == nullptr) or y += P^T N^-1 d (x == nullptr).
+// FFT path, fused: y += P^T N^-1 (P x) (d == nullptr) or y += P^T N^-1 d (x == nullptr), for
+// ncol columns (x or d column j at + j ldx, y column j at + j ldy; 0 = packed defaults).
 mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
-                             const int32_t* done, hipStream_t s);
+                             const int32_t* done, hipStream_t s, int32_t ncol = 1,
+                             int64_t ldx = 0, int64_t ldy = 0);
 mm_status launch_zero(double* y, int64_t n, hipStream_t s);
 
 // b = P^T N^-1 d (b overwritten).
@@ -203,6 +207,12 @@ mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s);
 
 // A x -> y (y overwritten), done-gated.
 mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s);
+// A X -> Y for ncol columns with leading dimensions ldx, ldy (Y overwritten).
+mm_status apply_A_multi(Plan* P, const double* x, int64_t ldx, double* y, int64_t ldy,
+                        int32_t ncol, hipStream_t s);
+// Stacked right-hand sides by the enlarged-CG recurrences (block.hip).
+mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* x,
+                      const mm_solve_opts* o, mm_solve_info* info, hipStream_t s);
 
 // Plan construction (plan.hip).
 mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out);

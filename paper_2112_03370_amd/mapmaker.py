@@ -58,12 +58,12 @@ class PlanInfo(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", _c_dbl), ("max_iter", _c_i32), ("use_x0", _c_i32),
-                ("check_every", _c_i32), ("use_graph", _c_i32)]
+                ("check_every", _c_i32), ("use_graph", _c_i32), ("block", _c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _c_i32), ("converged", _c_i32), ("relres", _c_dbl),
-                ("true_relres", _c_dbl), ("bnorm", _c_dbl), ("ms", _c_dbl)]
+                ("true_relres", _c_dbl), ("bnorm", _c_dbl), ("ms", _c_dbl), ("block", _c_i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -258,12 +258,14 @@ class Plan:
         return z
 
     def pcg_solve(self, d, x=None, tol=1e-8, max_iter=10000, use_x0=False, check_every=0,
-                  use_graph=True, stream=None, raise_on_error=True):
+                  use_graph=True, block=0, stream=None, raise_on_error=True):
+        """block 0/1: PCG per column; >= 2: columns solved together in groups of `block` by the
+        enlarged-CG recurrences; < 0: group size tuned among 8, 16, 32."""
         k = 1 if d.dim() == 1 else int(d.shape[0])
         ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
         x = x if x is not None else self._map(k)
         o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every,
-                      use_graph=int(use_graph))
+                      use_graph=int(use_graph), block=int(block))
         infos = (SolveInfo * max(1, k))()
         st = self._lib.mm_pcg_solve(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o), infos,
                                     _stream(stream))

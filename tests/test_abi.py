@@ -51,6 +51,7 @@ int main(void) {
   P(mm_geometry, fft_size) P(mm_geometry, flags) P(mm_plan_info_t, lambda_max)
   P(mm_plan_info_t, n_chunks)
   P(mm_solve_info, relres) P(mm_solve_info, ms) P(mm_solve_opts, use_graph)
+  P(mm_solve_opts, block) P(mm_solve_info, block)
   return 0;
 }
 """
@@ -76,5 +77,7 @@ int main(void) {
         "mm_solve_info.relres": M.SolveInfo.relres.offset,
         "mm_solve_info.ms": M.SolveInfo.ms.offset,
         "mm_solve_opts.use_graph": M.SolveOpts.use_graph.offset,
+        "mm_solve_opts.block": M.SolveOpts.block.offset,
+        "mm_solve_info.block": M.SolveInfo.block.offset,
     }
     assert {k: int(v) for k, v in got.items()} == exp

@@ -348,3 +348,56 @@ def test_planted_mistakes_are_caught(monkeypatch, mistake):
             return y
         monkeypatch.setattr(O, "noise_weight_fft", bad)
     assert not _pins_pass(plan, prob)
+
+
+# ------------------------------------------------------------------------------------------
+# Stacked right-hand sides: enlarged-CG (Alg. 2, Orthomin) recurrences
+# ------------------------------------------------------------------------------------------
+
+def _stack(seed, k, lam=64):
+    prob = synth.make_raster(cfg_id=70 + seed, n_dets=2, side=12, dwell=6, lam=lam, n_rhs=k)
+    plan = O.plan_from_problem(prob)
+    B = np.stack([O.rhs(plan, prob.d[j], "direct") for j in range(k)])
+    return prob, plan, B
+
+
+def test_block_ecg_with_one_column_is_alg1():
+    _, plan, B = _stack(0, 1)
+    r = O.block_ecg(plan, B)
+    p = O.pcg(plan, B[0])
+    assert r.block_iterations == p.iterations
+    np.testing.assert_allclose(r.x[0], p.x, rtol=0, atol=1e-12 * np.abs(p.x).max())
+
+
+def test_block_ecg_columns_solve_their_systems():
+    _, plan, B = _stack(1, 6)
+    n = 3 * plan.n_kept
+    A = np.array([O.apply_A(plan, e.reshape(-1, 3), "direct").reshape(-1) for e in np.eye(n)]).T
+    r = O.block_ecg(plan, B, tol=1e-10, apply=lambda v: O.apply_A(plan, v, "direct"))
+    kappa = np.linalg.cond(A)
+    for j in range(6):
+        xs = np.linalg.solve(A, B[j].reshape(-1))
+        err = np.linalg.norm(r.x[j].reshape(-1) - xs) / np.linalg.norm(xs)
+        assert r.converged[j] and err <= kappa * 1e-10
+    # the enlarged Krylov space never needs more iterations than the columns alone
+    assert r.block_iterations <= O.block_pcg(plan, B, tol=1e-10).iterations.max()
+
+
+def test_block_ecg_rank_deficient_and_zero_columns():
+    _, plan, B = _stack(2, 2)
+    B3 = np.stack([B[0], B[0], np.zeros_like(B[0]), B[1]])  # duplicated and zero columns
+    r = O.block_ecg(plan, B3)
+    ref = O.block_pcg(plan, B3)
+    assert r.converged.all() and r.iterations[2] == 0 and not np.any(r.x[2])
+    for j in (0, 1, 3):
+        err = np.linalg.norm(r.x[j] - ref.x[j]) / np.linalg.norm(ref.x[j])
+        assert err < 1e-6
+
+
+def test_sym_pinv_drops_null_directions():
+    rng = np.random.default_rng(3)
+    V = np.linalg.qr(rng.standard_normal((5, 5)))[0]
+    w = np.array([4.0, 2.0, 1.0, 1e-20, 0.0])
+    G = (V * w) @ V.T
+    want = (V[:, :3] / w[:3]) @ V[:, :3].T
+    np.testing.assert_allclose(O.sym_pinv(G), want, atol=1e-10)
