@@ -6,7 +6,10 @@ symbols), b = P^T N^-1 d, PCG to relative residual 1e-8, true-residual check, re
 value = n_samples * iterations / (seconds per step).
 
 Default workload: the ground-like scan (256 detectors x 2^20 samples, intervals of 2^16,
-512x512 patch, lambda = 8,192).  --config tiny runs the 4 x 65,536-sample raster instead.
+512x512 patch, lambda = 8,192).  --config tiny runs the 4 x 65,536-sample raster instead,
+--config satellite the long-band scan.  --config batched measures RHS solves/s for 64
+right-hand sides sharing P and N^-1 (stacked enlarged-CG solve with a tuned block size,
+against plain per-column PCG on the same GPU).
 One GPU only: --gpus N with N > 1 exits with a message.
 """
 
@@ -33,6 +36,8 @@ WORKLOADS = {
     "tiny": "tiny raster: 4 det x 65,536 samples, 64x64 patch, lambda 1024, f_knee 1 Hz",
     "satellite": "satellite-like: 32 det x 2^23 samples (268,435,456), intervals 2^20, 786,432 "
                  "pixels, HWP, lambda 32768, f_knee 0.05 Hz",
+    "batched": "batched multi-RHS: ground-like 64 det x 2^20 samples (67,108,864), intervals "
+               "2^16, 512x512 patch, lambda 8192, 64 right-hand sides sharing P and N^-1",
 }
 
 
@@ -78,6 +83,8 @@ def make_workload(name):
         return synth.make_config("tiny")
     if name == "satellite":
         return synth.make_config("satellite")
+    if name == "batched":
+        return synth.make_config("batched")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -111,6 +118,124 @@ def cpu_baseline(prob, target_s=15.0):
                       f"np.bincount single-threaded"}
 
 
+def fft_flops_per_sample(pinfo):
+    """FP32 flops per output sample of the overlap-save product: forward and inverse real FFTs
+    of N points (2 x 2.5 N log2 N) plus the pointwise spectrum work, over L = N - 2 lambda."""
+    n_fft = pinfo["fft_size"]
+    L = n_fft - 2 * pinfo["lambda_max"]
+    return (2 * 2.5 * n_fft * np.log2(n_fft) + 6 * n_fft) / L
+
+
+def run_batched(args, prob, mm, torch, dev, stream):
+    """Many right-hand sides sharing P and N^-1: solves/s of the stacked (enlarged-CG) solve with
+    a tuned block size, against plain per-column PCG on the same GPU and inputs."""
+    k = int(prob.d.shape[0])
+    d = torch.from_numpy(prob.d).to(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] {k} right-hand sides resident ({d.numel() * 4 / 2**30:.1f} GiB)")
+
+    def step(block, timing=False):
+        with torch.cuda.stream(stream):
+            plan = mm.Plan(pix_d, wq_d, wu_d, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                           prob.blk_band, prob.bands, det_offset=prob.det_offset, stream=stream)
+            if timing:
+                plan.set_timing(True)
+            x, infos = plan.pcg_solve(d, tol=args.tol, block=block, stream=stream)
+            kt = {q: plan.kernel_time(q) for q in range(4)} if timing else None
+            pinfo = plan.info
+            plan.close()
+        return x, infos, pinfo, kt
+
+    pix_d = torch.from_numpy(prob.pix).to(dev)
+    wq_d = torch.from_numpy(prob.wq).to(dev)
+    wu_d = torch.from_numpy(prob.wu).to(dev)
+    for w in range(args.warmup):
+        _, infos, _, _ = step(args.block)
+        log(f"[bench] warmup {w}: block sizes {sorted({i['block'] for i in infos})}, "
+            f"iterations {min(i['iterations'] for i in infos)}..{max(i['iterations'] for i in infos)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kts, all_infos = [], []
+    for q in range(args.steps):
+        x, infos, pinfo, kt = step(args.block, timing=True)
+        kts.append(kt)
+        all_infos.append(infos)
+        log(f"[bench] step {q}: block sizes {[i['block'] for i in infos][::8]}, iterations "
+            f"{min(i['iterations'] for i in infos)}..{max(i['iterations'] for i in infos)}, "
+            f"max true relres {max(i['true_relres'] for i in infos):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = k * args.steps / elapsed
+
+    # plain per-column PCG over the same inputs (one pass, same tolerance)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xp, pinfos, _, _ = step(0)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    plain = k / plain_s
+    diff = (x - xp).reshape(k, -1).norm(dim=1) / xp.reshape(k, -1).norm(dim=1).clamp_min(1e-300)
+    max_diff = float(diff.max())
+    log(f"[bench] batched {value:.2f} solves/s, plain {plain:.2f} solves/s "
+        f"(plain iterations {min(i['iterations'] for i in pinfos)}.."
+        f"{max(i['iterations'] for i in pinfos)}), max map rel diff {max_diff:.2e}")
+
+    # dominant kernel: the multi-column fused product; launches carry varying column counts, so
+    # the achieved rate is total work over total launch time
+    tot = sum(kt[1][0] for kt in kts)
+    cnt = sum(kt[1][1] for kt in kts)
+    col_applies = sum(sum(i["iterations"] + 3 for i in infos) for infos in all_infos)
+    n_s = prob.n_samples
+    flops = fft_flops_per_sample(pinfo) * n_s * col_applies
+    tflops = flops / (tot * 1e-3) / 1e12
+    hbm = 12.0 * n_s * cnt / (tot * 1e-3) / 1e9
+    roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+            "traffic": committed_traffic("apply_fused", "batched"),
+            "kernel": "apply_fused", "launches": cnt, "column_applies": col_applies,
+            "avg_launch_ms": round(tot / max(1, cnt), 4),
+            "avg_ms_per_column_apply": round(tot / max(1, col_applies), 4),
+            "pointing_hbm_gbs": round(hbm, 1), "pointing_hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        base = cpu_baseline(prob)
+        iters = float(np.mean([i["iterations"] for i in pinfos]))
+        # one plain solve of the whole workload costs iters (+1 residual) products of n_s samples
+        cpu = dict(base)
+        cpu["value"] = base["value"] / (n_s * (iters + 1))
+        cpu["unit"] = "RHS solves/s"
+        cpu["sample"] = (base["sample"] + f"; solves/s = rate / ({n_s} samples x "
+                         f"{iters + 1:.0f} products per plain solve)")
+        log(f"[bench] cpu baseline {cpu['value']:.3e} solves/s in {time.time() - t0:.1f} s")
+
+    per_rhs_iters = [i["iterations"] for i in all_infos[-1]]
+    return {
+        "metric": "batched solves/s at rel-res 1e-8",
+        "value": value,
+        "unit": "RHS solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 time-domain / f64 pixel-domain",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "n_samples": n_s, "n_rhs": k,
+                   "tol": args.tol, "n_kept": pinfo["n_kept"], "fft_size": pinfo["fft_size"],
+                   "block": args.block,
+                   "block_sizes_used": sorted({i["block"] for i in all_infos[-1]}),
+                   "iterations_min_max": [min(per_rhs_iters), max(per_rhs_iters)],
+                   "parallelism": "single GPU"},
+        "plain": {"solves_per_s": plain, "seconds": round(plain_s, 3),
+                  "iterations_mean": float(np.mean([i["iterations"] for i in pinfos])),
+                  "speedup": round(value / plain, 3), "max_map_rel_diff": max_diff,
+                  "max_true_relres_batched": max(i["true_relres"] for i in all_infos[-1]),
+                  "max_true_relres_plain": max(i["true_relres"] for i in pinfos)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +246,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="three-kernel FFT path (gather / Toeplitz / scatter) instead of fused")
+    ap.add_argument("--block", type=int, default=-1,
+                    help="batched workload: right-hand sides per block (-1: tuned among 8/16/32)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for PMC scaling)")
     args = ap.parse_args()
@@ -138,6 +265,10 @@ def main():
     t0 = time.time()
     prob = make_workload(args.config)
     log(f"[bench] generated {args.config}: {prob.n_samples} samples in {time.time() - t0:.1f} s")
+    if args.config == "batched":
+        stream = torch.cuda.Stream(device=dev)
+        print(json.dumps(run_batched(args, prob, mm, torch, dev, stream)), flush=True)
+        return
     pix = torch.from_numpy(prob.pix).to(dev)
     wq = torch.from_numpy(prob.wq).to(dev)
     wu = torch.from_numpy(prob.wu).to(dev)
@@ -184,7 +315,7 @@ def main():
     n_s = prob.n_samples
     tot = {k: sum(kt[k][0] for kt in kts) for k in range(4)}
     cnt = {k: sum(kt[k][1] for kt in kts) for k in range(4)}
-    fused = (not args.unfused) and pinfo["toeplitz_algo"] == mm.TOEPLITZ_FFT
+    fused = bool(pinfo["fused"])
     names = {0: "unpoint", 1: "apply_fused" if fused else "toeplitz", 2: "point", 3: "cg_vector"}
     dom = max(range(3), key=lambda k: tot[k])
     avg_ms = tot[dom] / max(1, cnt[dom])
@@ -202,9 +333,7 @@ def main():
             "kernel": names[dom], "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": algo_bytes}
     if dom == 1 and pinfo["toeplitz_algo"] == mm.TOEPLITZ_FFT:
-        n_fft = pinfo["fft_size"]
-        L = n_fft - 2 * pinfo["lambda_max"]
-        flops = n_s * (2 * 2.5 * n_fft * np.log2(n_fft) + 6 * n_fft) / L
+        flops = n_s * fft_flops_per_sample(pinfo)
         roof["fp32_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
         roof["fp32_frac"] = round(flops / (avg_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)
     per_kernel = {names[k]: {"total_ms": round(tot[k], 2), "launches": cnt[k],

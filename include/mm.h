@@ -112,6 +112,7 @@ typedef struct {
   int32_t fft_size;       /* 0 when not using the FFT product */
   int32_t n_blocks;
   int32_t n_chunks;       /* overlap-save segments (FFT) or tiles (direct) per product */
+  int32_t fused;          /* 1: gather, Toeplitz and scatter run as one kernel per segment */
 } mm_plan_info_t;
 
 typedef struct {
@@ -122,7 +123,8 @@ typedef struct {
   int32_t use_graph;      /* nonzero: replay iterations from a captured HIP graph */
   int32_t block;          /* right-hand sides solved together (Alg. 2 on stacked columns):
                              0 or 1 each column alone (Alg. 1); 2..32 that many at a time;
-                             < 0 tune among 8, 16, 32 on the first column groups */
+                             < 0 tune among 8, 16, 32 on the first column groups; the
+                             plan keeps the choice, and later tuned solves start with it */
 } mm_solve_opts;
 
 typedef struct {

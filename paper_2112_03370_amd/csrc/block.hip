@@ -13,7 +13,8 @@
 //
 // Block size: opts->block >= 2 fixes t; opts->block < 0 tunes it: the first column groups are
 // solved with t = 8, 16, 32 in turn (real work, not a rehearsal), the block size with the
-// lowest time per right-hand side then solves the remaining columns.
+// lowest time per right-hand side then solves the remaining columns and is kept in the plan,
+// so later tuned solves on the same plan start with it.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -492,17 +493,20 @@ mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* 
     ~Guard() { free_ws(w); }
   } guard{ws};
   std::vector<int> candidates;
-  if (o->block < 0) {
+  int best = 0;
+  if (o->block < 0 && P->tuned_block > 0) {
+    best = P->tuned_block;  // chosen by an earlier tuned solve on this plan
+  } else if (o->block < 0) {
     candidates = {8, 16, 32};
+    best = candidates[0];
   } else {
-    candidates = {std::min(std::max(2, static_cast<int>(o->block)), kMaxT)};
+    best = std::min(std::max(2, static_cast<int>(o->block)), kMaxT);
   }
   int32_t next = 0;
   size_t ci = 0;
-  int best = candidates[0];
   double best_cost = INFINITY;
   while (next < k) {
-    const bool tuning = o->block < 0 && ci < candidates.size();
+    const bool tuning = ci < candidates.size();
     const int t = tuning ? candidates[ci] : best;
     const int n = std::min<int32_t>(t, k - next);
     std::vector<int32_t> cols(n);
@@ -516,6 +520,7 @@ mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* 
         best = t;
       }
       ++ci;
+      if (ci == candidates.size() && best_cost < INFINITY) P->tuned_block = best;
     }
     next += n;
   }

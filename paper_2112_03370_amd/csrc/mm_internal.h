@@ -125,6 +125,7 @@ struct Plan {
   Tile* id_tiles = nullptr;     // the tiles of samples outside every block (weight 1)
   int32_t n_id_tiles = 0;
   bool fused = true;            // FFT path: gather + Toeplitz + scatter in one kernel
+  int32_t tuned_block = 0;      // block size chosen by the first tuned stacked solve (0: none)
   int32_t n_chunks = 0;
   int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
   int32_t n_id_seg = 0;

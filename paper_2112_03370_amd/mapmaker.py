@@ -52,7 +52,7 @@ class PlanInfo(ctypes.Structure):
         ("n_samples", _c_i64), ("n_pix_global", _c_i64), ("n_obs", _c_i64), ("n_kept", _c_i64),
         ("n_excised", _c_i64), ("n_gap_samples", _c_i64), ("device_bytes", _c_i64),
         ("lambda_max", _c_i32), ("toeplitz_algo", _c_i32), ("fft_size", _c_i32),
-        ("n_blocks", _c_i32), ("n_chunks", _c_i32),
+        ("n_blocks", _c_i32), ("n_chunks", _c_i32), ("fused", _c_i32),
     ]
 
 

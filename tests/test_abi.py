@@ -49,7 +49,7 @@ int main(void) {
   printf("mm_solve_info %zu\n", sizeof(mm_solve_info));
   P(mm_geometry, n_pix_global) P(mm_geometry, band_coef) P(mm_geometry, cond_max)
   P(mm_geometry, fft_size) P(mm_geometry, flags) P(mm_plan_info_t, lambda_max)
-  P(mm_plan_info_t, n_chunks)
+  P(mm_plan_info_t, n_chunks) P(mm_plan_info_t, fused)
   P(mm_solve_info, relres) P(mm_solve_info, ms) P(mm_solve_opts, use_graph)
   P(mm_solve_opts, block) P(mm_solve_info, block)
   return 0;
@@ -74,6 +74,7 @@ int main(void) {
         "mm_geometry.flags": M.Geometry.flags.offset,
         "mm_plan_info_t.lambda_max": M.PlanInfo.lambda_max.offset,
         "mm_plan_info_t.n_chunks": M.PlanInfo.n_chunks.offset,
+        "mm_plan_info_t.fused": M.PlanInfo.fused.offset,
         "mm_solve_info.relres": M.SolveInfo.relres.offset,
         "mm_solve_info.ms": M.SolveInfo.ms.offset,
         "mm_solve_opts.use_graph": M.SolveOpts.use_graph.offset,

@@ -111,6 +111,12 @@ def test_block_tuned_many_columns(gpu_lib):
         want = O.pcg(ref, O.rhs(ref, prob.d[j]), tol=1e-8).x
         err = float(_rel(m[j], want))
         assert err <= 1e-6, (j, err)
+    # the plan keeps the tuned size: a second tuned solve uses it for every group
+    x2, infos2 = plan.pcg_solve(_dev(prob.d[:20]), tol=1e-8, block=-1)
+    sizes = {i["block"] for i in infos2}
+    assert len(sizes) == 1 and sizes <= {8, 16, 32}, sizes
+    err = float(_rel(x2.cpu().numpy(), m[:20]))
+    assert err <= 1e-6, err
 
 
 def test_block_zero_and_repeated_columns(gpu_lib):
