@@ -48,6 +48,7 @@ def log(*a):
 KERNEL_SOURCES = {
     "apply_fused": ("apply_fused.hip", "fft_lds.h", "wave_runs.h"),
     "toeplitz": ("toeplitz.hip", "fft_lds.h"),
+    "toeplitz_long": ("toeplitz_long.hip", "fft_lds.h"),
     "unpoint": ("pointing.hip",),
     "point": ("pointing.hip", "wave_runs.h"),
 }
@@ -316,7 +317,8 @@ def main():
     tot = {k: sum(kt[k][0] for kt in kts) for k in range(4)}
     cnt = {k: sum(kt[k][1] for kt in kts) for k in range(4)}
     fused = bool(pinfo["fused"])
-    names = {0: "unpoint", 1: "apply_fused" if fused else "toeplitz", 2: "point", 3: "cg_vector"}
+    toep = "toeplitz_long" if pinfo["fft_size"] > (1 << 15) else "toeplitz"
+    names = {0: "unpoint", 1: "apply_fused" if fused else toep, 2: "point", 3: "cg_vector"}
     dom = max(range(3), key=lambda k: tot[k])
     avg_ms = tot[dom] / max(1, cnt[dom])
     # algorithmic bytes per sample and launch (one launch covers n_samples): pointing is 12 B
