@@ -22,7 +22,9 @@
  *     the number of kept pixels of the plan, ordered by ascending global pixel id.
  *   - Time-domain vectors are FP32 with n_samples entries per right-hand side, detector-major.
  *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Asynchronous calls
- *     are ordered on that stream; calls on one plan must not overlap (they share its workspace).
+ *     are ordered on that stream; calls on one plan must not overlap (they share its workspace;
+ *     mm_pcg_solve serializes itself, the asynchronous calls are ordered by the caller).  The
+ *     serving calls below run solves on one plan concurrently, each with its own workspace.
  */
 #ifndef MM_H
 #define MM_H
@@ -205,6 +207,84 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
  * since the last reset.  Synchronous. */
 mm_status mm_set_timing(mm_plan_t* plan, int32_t enable);
 mm_status mm_kernel_time(mm_plan_t* plan, int32_t kind, double* total_ms, int64_t* launches);
+
+/* ---- Serving: many solves of uneven size, continuously batched on one GPU ------------------
+ *
+ * A server keeps plans on the device (a cache keyed by a caller-chosen 64-bit geometry key) and
+ * runs submitted solves on n_slots host threads, each with its own HIP stream and per-request
+ * workspace, so the solves of different requests overlap on the device.  A request is admitted
+ * when a slot is free and its workspace fits the device-memory budget next to the cached plans
+ * and the running requests; a request that does not fit lets later ones start (up to
+ * max_bypass times, then it waits at the head of the queue).  Idle workspaces are kept per plan
+ * for reuse and released, then unpinned plans evicted least recently used first, when memory is
+ * needed.  Each request runs exactly the computation of mm_pcg_solve on its own (its columns
+ * never share a block with another request's), so its result does not depend on the mix apart
+ * from the order of FP64 atomic additions. */
+typedef struct {
+  int64_t hbm_budget;    /* device bytes for cached plans + request workspaces; <= 0: 80% of
+                            the free device memory at creation */
+  int32_t n_slots;       /* solves running at once; <= 0: 4 */
+  int32_t max_bypass;    /* later requests that may start before a waiting one; < 0: 16 */
+} mm_server_opts;
+
+typedef struct {
+  double queued_ms;      /* submit -> start on a slot */
+  double run_ms;         /* start -> result ready */
+  double total_ms;       /* submit -> result ready */
+  int32_t slot;          /* slot that ran the request */
+  int32_t pad;
+} mm_request_times;
+
+typedef struct {
+  int64_t hbm_budget;
+  int64_t bytes_in_use;  /* cached plans + workspaces (idle and running) */
+  int64_t peak_bytes;
+  int64_t submitted;
+  int64_t completed;
+  int64_t plan_hits;
+  int64_t plan_misses;
+  int64_t evictions;
+  int32_t queued;
+  int32_t running;
+  int32_t peak_running;  /* most requests that ran at once */
+  int32_t n_plans;
+} mm_server_stats_t;
+
+/* Create a server on the current device.  opts may be NULL (defaults).  Errors: MM_ERR_INVALID,
+ * MM_ERR_HIP. */
+mm_status mm_server_create(const mm_server_opts* opts, mm_server_t** out);
+
+/* Stop the server: queued requests are dropped (never run), running solves finish, then every
+ * cached plan and workspace is released.  Tickets are invalid afterwards.  NULL is accepted. */
+mm_status mm_server_destroy(mm_server_t* server);
+
+/* Make the plan of geometry g available under `key` (mm_plan semantics; the geometry's device
+ * arrays must stay valid until this call returns).  A cached key is a hit and g is not read (it
+ * may be NULL then).  info (HOST, may be NULL) receives the plan's mm_plan_info.  Blocks while
+ * another thread builds the same key.  Errors: those of mm_plan; MM_ERR_INVALID (g NULL on a
+ * miss); MM_ERR_BUDGET (the plan alone exceeds the budget). */
+mm_status mm_server_plan(mm_server_t* server, const mm_geometry* g, uint64_t key,
+                         mm_plan_info_t* info);
+
+/* Queue a solve of k right-hand sides on the cached plan `key`; arguments as mm_pcg_solve
+ * (d, x DEVICE, caller-owned; they must stay valid, and x untouched, until mm_poll reports the
+ * result).  Non-blocking; *ticket identifies the request.  The plan stays cached while the
+ * request is queued or running.  Errors: MM_ERR_NOT_FOUND (key not cached), MM_ERR_INVALID,
+ * MM_ERR_BUDGET (plan + workspace can never fit the budget). */
+mm_status mm_submit(mm_server_t* server, uint64_t key, const float* d, int32_t k, int64_t ld_d,
+                    double* x, const mm_solve_opts* opts, uint64_t* ticket);
+
+/* MM_PENDING while the request is queued or running.  Otherwise the solve's status (as
+ * mm_pcg_solve), with info (HOST, k entries, may be NULL) and times (may be NULL) filled; the
+ * ticket is released by that call.  MM_ERR_NOT_FOUND for an unknown or released ticket. */
+mm_status mm_poll(mm_server_t* server, uint64_t ticket, mm_solve_info* info,
+                  mm_request_times* times);
+
+/* Like mm_poll but blocks until the request has finished. */
+mm_status mm_wait(mm_server_t* server, uint64_t ticket, mm_solve_info* info,
+                  mm_request_times* times);
+
+mm_status mm_server_stats(mm_server_t* server, mm_server_stats_t* out);
 
 const char* mm_status_string(mm_status s);
 const char* mm_last_error(void);

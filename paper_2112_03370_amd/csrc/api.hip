@@ -176,7 +176,7 @@ mm_status mm_noise_weight(const mm_plan_t* plan, const float* t, float* u, void*
   MM_TRY(check_device(P));
   if (P->n_samples > 0 && (!t || !u)) return fail(MM_ERR_INVALID, "NULL vector");
   if (P->n_samples > 0 && t == u) return fail(MM_ERR_INVALID, "t and u must not alias");
-  return guarded([&]() -> mm_status { return launch_noise_weight(P, t, u, nullptr, as_stream(stream)); });
+  return guarded([&]() -> mm_status { return launch_noise_weight(P, t, u, P->work.scratch, nullptr, as_stream(stream)); });
 }
 
 mm_status mm_point(const mm_plan_t* plan, const float* u, double* y, void* stream) {
@@ -198,7 +198,7 @@ mm_status mm_rhs(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d,
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
-    for (int32_t j = 0; j < k; ++j) MM_TRY(compute_rhs(P, d + j * ld_d, b + j * 3 * P->n_kept, s));
+    for (int32_t j = 0; j < k; ++j) MM_TRY(compute_rhs(P, P->work, d + j * ld_d, b + j * 3 * P->n_kept, s));
     return MM_OK;
   });
 }
@@ -213,7 +213,7 @@ mm_status mm_apply_A(const mm_plan_t* plan, const double* x, double* y, int32_t 
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
-    return apply_A_multi(P, x, 3 * P->n_kept, y, 3 * P->n_kept, k, s);
+    return apply_A_multi(P, P->work, x, 3 * P->n_kept, y, 3 * P->n_kept, k, s);
   });
 }
 
@@ -246,13 +246,13 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
   return guarded([&]() -> mm_status {
     if (opts && opts->block != 0 && opts->block != 1 && k > 0) {
       if (opts->use_x0) return fail(MM_ERR_INVALID, "use_x0 is not supported with block != 0/1");
-      return block_solve(P, d, k, ld_d, x, opts, info, s);
+      return block_solve(P, P->work, d, k, ld_d, x, opts, info, s);
     }
     mm_status worst = MM_OK;
     std::string msg;
     for (int32_t j = 0; j < k; ++j) {
       mm_solve_info tmp{};
-      mm_status st = pcg_solve(P, d + j * ld_d, x + j * 3 * P->n_kept, opts, info ? &info[j] : &tmp, s);
+      mm_status st = pcg_solve(P, P->work, d + j * ld_d, x + j * 3 * P->n_kept, opts, info ? &info[j] : &tmp, s);
       if (st == MM_ERR_HIP || st == MM_ERR_OOM || st == MM_ERR_INVALID || st == MM_ERR_UNSUPPORTED)
         return st;
       if (st != MM_OK && worst == MM_OK) {

@@ -303,10 +303,10 @@ mm_status ensure_ws(Plan* P, BlockWs& ws, int t) {
   for (void* p : {static_cast<void*>(ws.R), static_cast<void*>(ws.Z), static_cast<void*>(ws.W),
                   static_cast<void*>(ws.MR), static_cast<void*>(ws.small),
                   static_cast<void*>(ws.partial), static_cast<void*>(ws.cols)})
-    if (p) (void)hipFree(p);
+    dev_free(p);
   ws = BlockWs{};
   auto alloc = [&](void** p, size_t bytes) -> mm_status {
-    if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+    if (dev_malloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
       *p = nullptr;
       return fail(MM_ERR_OOM, "hipMalloc (block workspace) failed");
     }
@@ -330,7 +330,7 @@ void free_ws(BlockWs& ws) {
   for (void* p : {static_cast<void*>(ws.R), static_cast<void*>(ws.Z), static_cast<void*>(ws.W),
                   static_cast<void*>(ws.MR), static_cast<void*>(ws.small),
                   static_cast<void*>(ws.partial), static_cast<void*>(ws.cols)})
-    if (p) (void)hipFree(p);
+    dev_free(p);
   ws = BlockWs{};
 }
 
@@ -363,7 +363,7 @@ mm_status col_norms(const double* B, const double* Y, int t, int64_t nu, BlockWs
 }
 
 // Solve the columns `cols` (at most kMaxT) together.
-mm_status solve_group(Plan* P, const float* d, int64_t ld_d, double* x,
+mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x,
                       const std::vector<int32_t>& cols, double tol, int max_iter,
                       mm_solve_info* info, int block_used, BlockWs& ws, hipStream_t s) {
   const int t = static_cast<int>(cols.size());
@@ -374,7 +374,7 @@ mm_status solve_group(Plan* P, const float* d, int64_t ld_d, double* x,
   // R_j = b_j = P^T N^-1 d_j, X_j = 0
   MM_HIP_TRY(hipMemcpyAsync(ws.cols, cols.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_zero_cols, dim3(rows_grid(t * nu)), dim3(kThreads), 0, s, x, ws.cols, t, nu);
-  for (int j = 0; j < t; ++j) MM_TRY(compute_rhs(P, d + cols[j] * ld_d, ws.R + j * nu, s));
+  for (int j = 0; j < t; ++j) MM_TRY(compute_rhs(P, Wk, d + cols[j] * ld_d, ws.R + j * nu, s));
   std::vector<double> bb;
   MM_TRY(col_norms(ws.R, nullptr, t, nu, ws, bb, s));
   std::vector<double> bnorm(t);
@@ -404,7 +404,7 @@ mm_status solve_group(Plan* P, const float* d, int64_t ld_d, double* x,
   }
   int k = 0;
   while (ta > 0 && k < max_iter) {
-    MM_TRY(apply_A_multi(P, ws.Z, nu, ws.W, nu, tz, s));  // W = A Z
+    MM_TRY(apply_A_multi(P, Wk, ws.Z, nu, ws.W, nu, tz, s));  // W = A Z
     MM_TRY(gram(ws.Z, tz, ws.W, tz, nu, ws, G, s));       // G = Z^T W
     MM_TRY(gram(ws.Z, tz, ws.R, ta, nu, ws, H, s));       // H1 = Z^T R
     sym_pinv(G, tz, 1e-12, Gi);
@@ -461,8 +461,8 @@ mm_status solve_group(Plan* P, const float* d, int64_t ld_d, double* x,
   std::vector<double> tr(t, 0.0);
   MM_HIP_TRY(hipMemcpyAsync(ws.cols, cols.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
   for (int j = 0; j < t; ++j) {
-    MM_TRY(compute_rhs(P, d + cols[j] * ld_d, ws.R + j * nu, s));
-    MM_TRY(apply_A(P, x + static_cast<int64_t>(cols[j]) * nu, ws.W + j * nu, nullptr, s));
+    MM_TRY(compute_rhs(P, Wk, d + cols[j] * ld_d, ws.R + j * nu, s));
+    MM_TRY(apply_A(P, Wk, x + static_cast<int64_t>(cols[j]) * nu, ws.W + j * nu, nullptr, s));
   }
   MM_TRY(col_norms(ws.R, ws.W, t, nu, ws, tr, s));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ev).count();
@@ -481,7 +481,7 @@ mm_status solve_group(Plan* P, const float* d, int64_t ld_d, double* x,
 
 }  // namespace
 
-mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* x,
+mm_status block_solve(Plan* P, Work& Wk, const float* d, int32_t k, int64_t ld_d, double* x,
                       const mm_solve_opts* o, mm_solve_info* info, hipStream_t s) {
   const double tol = o->tol > 0 ? o->tol : 1e-8;
   const int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
@@ -494,8 +494,8 @@ mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* 
   } guard{ws};
   std::vector<int> candidates;
   int best = 0;
-  if (o->block < 0 && P->tuned_block > 0) {
-    best = P->tuned_block;  // chosen by an earlier tuned solve on this plan
+  if (o->block < 0 && P->tuned_block.load() > 0) {
+    best = P->tuned_block.load();  // chosen by an earlier tuned solve on this plan
   } else if (o->block < 0) {
     candidates = {8, 16, 32};
     best = candidates[0];
@@ -512,7 +512,7 @@ mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* 
     std::vector<int32_t> cols(n);
     std::iota(cols.begin(), cols.end(), next);
     const auto t0 = std::chrono::steady_clock::now();
-    MM_TRY(solve_group(P, d, ld_d, x, cols, tol, max_iter, inf, t, ws, s));
+    MM_TRY(solve_group(P, Wk, d, ld_d, x, cols, tol, max_iter, inf, t, ws, s));
     const double cost = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / n;
     if (tuning) {
       if (n == t && cost < best_cost) {

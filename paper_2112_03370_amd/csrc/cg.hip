@@ -243,27 +243,27 @@ __global__ __launch_bounds__(kThreads) void k_reduce_to(double* out, const doubl
 }
 
 // One PCG iteration (all launches gated by state->done).
-mm_status iteration(Plan* P, double* x, hipStream_t s) {
-  const int32_t* done = &P->state->done;
-  const int nrb = P->n_red_blocks;
+mm_status iteration(Plan* P, Work& W, double* x, hipStream_t s) {
+  const int32_t* done = &W.state->done;
+  const int nrb = W.nrb;
   const int64_t nk = P->n_kept;
   if (P->lambda_max == 0) {
-    MM_TRY(launch_diag_apply(P, P->p, nullptr, P->q, done, s));  // q was zeroed by k_update
+    MM_TRY(launch_diag_apply(P, W.p, nullptr, W.q, done, s));  // q was zeroed by k_update
   } else if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
-    MM_TRY(launch_apply_fused(P, P->p, nullptr, P->q, done, s));
+    MM_TRY(launch_apply_fused(P, W.p, nullptr, W.q, done, s));
   } else {
-    MM_TRY(launch_unpoint(P, P->p, P->t, done, s));
-    MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
-    MM_TRY(launch_point(P, P->u, P->q, false, done, s));
+    MM_TRY(launch_unpoint(P, W.p, W.t, done, s));
+    MM_TRY(launch_noise_weight(P, W.t, W.u, W.scratch, done, s));
+    MM_TRY(launch_point(P, W.u, W.q, false, done, s));
   }
   TimedLaunch tl(P, K_CG, s);
-  hipLaunchKernelGGL(k_dot_pq, dim3(nrb), dim3(kThreads), 0, s, P->p, P->q, 3 * nk, P->partial,
-                     P->state);
-  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kThreads), 0, s, P->state, P->partial, nrb);
-  hipLaunchKernelGGL(k_update, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, P->r, P->z, P->p,
-                     P->q, nk, P->partial, nrb, P->state);
-  hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, P->state, P->partial, nrb);
-  hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, P->z, P->p, 3 * nk, P->state);
+  hipLaunchKernelGGL(k_dot_pq, dim3(nrb), dim3(kThreads), 0, s, W.p, W.q, 3 * nk, W.partial,
+                     W.state);
+  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
+  hipLaunchKernelGGL(k_update, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z, W.p,
+                     W.q, nk, W.partial, nrb, W.state);
+  hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
+  hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, W.z, W.p, 3 * nk, W.state);
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
 }
@@ -295,7 +295,7 @@ mm_status launch_precond_multi(Plan* P, const double* r, double* z, int32_t ncol
   return MM_OK;
 }
 
-mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s) {
+mm_status compute_rhs(Plan* P, Work& W, const float* d, double* b, hipStream_t s) {
   if (P->lambda_max == 0) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
     return launch_diag_apply(P, nullptr, d, b, nullptr, s);
@@ -304,12 +304,13 @@ mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
     return launch_apply_fused(P, nullptr, d, b, nullptr, s);
   }
-  MM_TRY(launch_mask_data(P, d, P->t, s));
-  MM_TRY(launch_noise_weight(P, P->t, P->u, nullptr, s));
-  return launch_point(P, P->u, b, true, nullptr, s);
+  MM_TRY(launch_mask_data(P, d, W.t, s));
+  MM_TRY(launch_noise_weight(P, W.t, W.u, W.scratch, nullptr, s));
+  return launch_point(P, W.u, b, true, nullptr, s);
 }
 
-mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s) {
+mm_status apply_A(Plan* P, Work& W, const double* x, double* y, const int32_t* done,
+                  hipStream_t s) {
   if (P->lambda_max == 0) {
     MM_TRY(launch_zero(y, 3 * P->n_kept, s));
     return launch_diag_apply(P, x, nullptr, y, done, s);
@@ -318,24 +319,24 @@ mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipS
     MM_TRY(launch_zero(y, 3 * P->n_kept, s));
     return launch_apply_fused(P, x, nullptr, y, done, s);
   }
-  MM_TRY(launch_unpoint(P, x, P->t, done, s));
-  MM_TRY(launch_noise_weight(P, P->t, P->u, done, s));
-  MM_TRY(launch_point(P, P->u, y, true, done, s));
+  MM_TRY(launch_unpoint(P, x, W.t, done, s));
+  MM_TRY(launch_noise_weight(P, W.t, W.u, W.scratch, done, s));
+  MM_TRY(launch_point(P, W.u, y, true, done, s));
   return MM_OK;
 }
 
-mm_status apply_A_multi(Plan* P, const double* x, int64_t ldx, double* y, int64_t ldy,
+mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* y, int64_t ldy,
                         int32_t ncol, hipStream_t s) {
   if (ncol <= 0 || P->n_kept == 0) return MM_OK;
   if (P->lambda_max != 0 && P->algo == MM_TOEPLITZ_FFT && P->fused) {
     for (int32_t j = 0; j < ncol; ++j) MM_TRY(launch_zero(y + j * ldy, 3 * P->n_kept, s));
     return launch_apply_fused(P, x, nullptr, y, nullptr, s, ncol, ldx, ldy);
   }
-  for (int32_t j = 0; j < ncol; ++j) MM_TRY(apply_A(P, x + j * ldx, y + j * ldy, nullptr, s));
+  for (int32_t j = 0; j < ncol; ++j) MM_TRY(apply_A(P, W, x + j * ldx, y + j * ldy, nullptr, s));
   return MM_OK;
 }
 
-mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
+mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_opts* o,
                     mm_solve_info* info, hipStream_t caller) {
   mm_solve_opts opts{};
   if (o) opts = *o;
@@ -349,7 +350,7 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
   }
   const double tol = opts.tol > 0 ? opts.tol : 1e-8;
   const int max_iter = opts.max_iter > 0 ? opts.max_iter : 10000;
-  const int nrb = P->n_red_blocks;
+  const int nrb = W.nrb;
   const int64_t nk = P->n_kept;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   MM_HIP_TRY(hipEventCreate(&ev0));
@@ -364,12 +365,12 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
   MM_HIP_TRY(hipEventRecord(ev0, s));
 
   // b = P^T N^-1 d
-  P->timing.tag = 0;
-  MM_TRY(compute_rhs(P, d, P->b, s));
-  if (opts.use_x0) MM_TRY(apply_A(P, x, P->q, nullptr, s));
-  hipLaunchKernelGGL(k_init, dim3(nrb), dim3(kThreads), 0, s, P->minv, P->b, P->q, P->r, P->z,
-                     P->p, P->q, x, opts.use_x0 ? 1 : 0, nk, P->partial, nrb);
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, P->state, P->partial, nrb, tol,
+  if (P->timing.enabled) P->timing.tag = 0;
+  MM_TRY(compute_rhs(P, W, d, W.b, s));
+  if (opts.use_x0) MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
+  hipLaunchKernelGGL(k_init, dim3(nrb), dim3(kThreads), 0, s, P->minv, W.b, W.q, W.r, W.z,
+                     W.p, W.q, x, opts.use_x0 ? 1 : 0, nk, W.partial, nrb);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb, tol,
                      max_iter);
   MM_HIP_TRY(hipGetLastError());
 
@@ -383,64 +384,76 @@ mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
   struct GraphGuard {
     hipGraphExec_t* e;
     ~GraphGuard() {
-      if (*e) (void)hipGraphExecDestroy(*e);
+      if (*e) {
+        std::unique_lock<std::shared_mutex> lock(alloc_gate());
+        (void)hipGraphExecDestroy(*e);
+      }
     }
   } gg{&gexec};
   int queued = 0;
   while (true) {
-    MM_HIP_TRY(hipMemcpyAsync(P->h_state, P->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipMemcpyAsync(W.h_state, W.state, sizeof(CgState), hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
-    if (P->h_state->done) break;
+    if (W.h_state->done) break;
     if (queued >= max_iter + 1) break;  // safety: the device stops at max_iter
     if (use_graph) {
       if (gexec == nullptr || graph_chunk != chunk) {
         if (gexec) {
-          MM_HIP_TRY(hipGraphExecDestroy(gexec));
+          std::unique_lock<std::shared_mutex> lock(alloc_gate());
+          const hipError_t de = hipGraphExecDestroy(gexec);
           gexec = nullptr;
+          if (de != hipSuccess) return fail(MM_ERR_HIP, std::string("graph destroy: ") + hipGetErrorString(de));
         }
         hipGraph_t graph = nullptr;
+        std::shared_lock<std::shared_mutex> gate(alloc_gate());
         MM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         mm_status st = MM_OK;
-        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, x, s);
+        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, s);
         hipError_t ce = hipStreamEndCapture(s, &graph);
+        gate.unlock();
         if (st != MM_OK) {
           if (graph) (void)hipGraphDestroy(graph);
           return st;
         }
         if (ce != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-        hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
+        hipError_t ie;
+        {
+          // instantiation may allocate device memory: keep it apart from other captures
+          std::unique_lock<std::shared_mutex> lock(alloc_gate());
+          ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+        }
         if (ie != hipSuccess) return fail(MM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
         graph_chunk = chunk;
       }
       MM_HIP_TRY(hipGraphLaunch(gexec, s));
     } else {
       for (int i = 0; i < chunk; ++i) {
-        P->timing.tag = queued + i + 1;
-        MM_TRY(iteration(P, x, s));
+        if (P->timing.enabled) P->timing.tag = queued + i + 1;
+        MM_TRY(iteration(P, W, x, s));
       }
-      P->timing.tag = 0;
+      if (P->timing.enabled) P->timing.tag = 0;
     }
     queued += chunk;
     if (opts.check_every <= 0 && !P->timing.enabled && chunk < 16) chunk *= 2;
   }
 
   // True residual with one more product.
-  const CgState st = *P->h_state;
+  const CgState st = *W.h_state;
   if (P->timing.enabled) timing_drop_after(P, st.iter);
   double true_rr = 0.0;
   if (nk > 0 && st.bb > 0.0) {
-    MM_TRY(apply_A(P, x, P->q, nullptr, s));
-    hipLaunchKernelGGL(k_resid, dim3(nrb), dim3(kThreads), 0, s, P->b, P->q, 3 * nk, P->partial);
-    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kThreads), 0, s, &P->state->spare, P->partial,
+    MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
+    hipLaunchKernelGGL(k_resid, dim3(nrb), dim3(kThreads), 0, s, W.b, W.q, 3 * nk, W.partial);
+    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kThreads), 0, s, &W.state->spare, W.partial,
                        nrb);
     MM_HIP_TRY(hipGetLastError());
-    MM_HIP_TRY(hipMemcpyAsync(&P->h_state->spare, &P->state->spare, sizeof(double),
+    MM_HIP_TRY(hipMemcpyAsync(&W.h_state->spare, &W.state->spare, sizeof(double),
                               hipMemcpyDeviceToHost, s));
   }
   MM_HIP_TRY(hipEventRecord(ev1, s));
   MM_HIP_TRY(hipStreamSynchronize(s));
-  true_rr = P->h_state->spare;
+  true_rr = W.h_state->spare;
   float ms = 0.0f;
   MM_HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
   if (info) {

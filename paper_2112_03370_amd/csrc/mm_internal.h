@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -87,6 +89,37 @@ struct Timing {
 };
 
 
+// Per-solve device workspace: time-domain buffers (unfused and direct products), long-segment
+// tiles, the PCG vectors and scalars.  A plan holds one for the plain calls; a server gives every
+// running request its own, so that solves on one plan can overlap.
+struct Work {
+  float* t = nullptr;           // [n_samples] (only when the product is not fused)
+  float* u = nullptr;
+  float2* scratch = nullptr;    // long segments: one NC-point complex tile per segment
+  double* r = nullptr;          // [3 n_kept] each
+  double* z = nullptr;
+  double* p = nullptr;
+  double* q = nullptr;
+  double* b = nullptr;
+  double* partial = nullptr;    // reduction partials, 4 slots of nrb
+  int32_t nrb = 0;
+  CgState* state = nullptr;
+  CgState* h_state = nullptr;   // pinned host mirror
+  int64_t bytes = 0;
+};
+
+struct Plan;
+int64_t work_bytes(const Plan* P);
+mm_status work_alloc(const Plan* P, Work* W);
+void work_free(Work* W);
+
+// Device allocation and release.  Allocation calls and graph captures exclude each other
+// (gate_capture / gate_alloc), so that solves capturing graphs on one thread never see a
+// concurrent hipMalloc / hipFree of another thread (a server runs both at once).
+std::shared_mutex& alloc_gate();
+hipError_t dev_malloc(void** p, size_t bytes);
+void dev_free(void* p);
+
 struct Plan {
   int device = 0;
   int64_t n_samples = 0;
@@ -119,30 +152,18 @@ struct Plan {
   float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
   float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
-  float2* scratch = nullptr;    // long segments: one NC-point complex tile per segment
   Tile* tiles = nullptr;        // <= 4096-sample tiles with their diagonal weight c_0
   int32_t n_tiles = 0;
   Tile* id_tiles = nullptr;     // the tiles of samples outside every block (weight 1)
   int32_t n_id_tiles = 0;
   bool fused = true;            // FFT path: gather + Toeplitz + scatter in one kernel
-  int32_t tuned_block = 0;      // block size chosen by the first tuned stacked solve (0: none)
+  std::atomic<int32_t> tuned_block{0};  // block size chosen by a tuned stacked solve (0: none)
   int32_t n_chunks = 0;
   int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
   int32_t n_id_seg = 0;
   std::vector<int64_t> h_id_seg;
 
-  // workspace (device)
-  float* t = nullptr;
-  float* u = nullptr;
-  double* r = nullptr;
-  double* z = nullptr;
-  double* p = nullptr;
-  double* q = nullptr;
-  double* b = nullptr;
-  double* partial = nullptr;    // reduction partials, 4 slots of n_red_blocks
-  int32_t n_red_blocks = 0;
-  CgState* state = nullptr;
-  CgState* h_state = nullptr;   // pinned host mirror
+  Work work;                    // workspace of the plain calls (serialized by mu)
   hipStream_t aux = nullptr;    // plan-owned stream for graph replay when the caller's is null
 
   Timing timing;
@@ -158,7 +179,7 @@ template <class T>
 mm_status dalloc(Plan* P, T** ptr, size_t count) {
   *ptr = nullptr;
   if (count == 0) return MM_OK;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
+  hipError_t e = dev_malloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
   if (e != hipSuccess) {
     *ptr = nullptr;
     return fail(MM_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
@@ -183,8 +204,8 @@ struct TimedLaunch {
 
 mm_status launch_unpoint(Plan* P, const double* x, float* t, const int32_t* done, hipStream_t s);
 mm_status launch_mask_data(Plan* P, const float* d, float* t, hipStream_t s);
-mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* done,
-                              hipStream_t s);
+mm_status launch_noise_weight(Plan* P, const float* t, float* u, float2* scratch,
+                              const int32_t* done, hipStream_t s);
 mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, const int32_t* done,
                        hipStream_t s);
 mm_status launch_precond(Plan* P, const double* r, double* z, hipStream_t s);
@@ -204,23 +225,24 @@ mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y
 mm_status launch_zero(double* y, int64_t n, hipStream_t s);
 
 // b = P^T N^-1 d (b overwritten).
-mm_status compute_rhs(Plan* P, const float* d, double* b, hipStream_t s);
+mm_status compute_rhs(Plan* P, Work& W, const float* d, double* b, hipStream_t s);
 
 // A x -> y (y overwritten), done-gated.
-mm_status apply_A(Plan* P, const double* x, double* y, const int32_t* done, hipStream_t s);
+mm_status apply_A(Plan* P, Work& W, const double* x, double* y, const int32_t* done,
+                  hipStream_t s);
 // A X -> Y for ncol columns with leading dimensions ldx, ldy (Y overwritten).
-mm_status apply_A_multi(Plan* P, const double* x, int64_t ldx, double* y, int64_t ldy,
+mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* y, int64_t ldy,
                         int32_t ncol, hipStream_t s);
 // Stacked right-hand sides by the enlarged-CG recurrences (block.hip).
-mm_status block_solve(Plan* P, const float* d, int32_t k, int64_t ld_d, double* x,
+mm_status block_solve(Plan* P, Work& W, const float* d, int32_t k, int64_t ld_d, double* x,
                       const mm_solve_opts* o, mm_solve_info* info, hipStream_t s);
 
 // Plan construction (plan.hip).
 mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out);
-void destroy_plan(Plan* P);
+void destroy_plan(Plan* P);  // releases the device memory and deletes P
 
 // PCG (cg.hip).
-mm_status pcg_solve(Plan* P, const float* d, double* x, const mm_solve_opts* o,
+mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_opts* o,
                     mm_solve_info* info, hipStream_t s);
 
 // FFT sizing helpers (toeplitz.hip).
@@ -230,7 +252,7 @@ int32_t max_direct_lambda();
 // Long segments (toeplitz_long.hip): N = 2^16, 2^17 through a global tile per segment.
 bool long_fft_size(int32_t n);
 int32_t long_fine_size();
-mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, const int32_t* done,
-                               hipStream_t s);
+mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, float2* scratch,
+                               const int32_t* done, hipStream_t s);
 
 }  // namespace mm

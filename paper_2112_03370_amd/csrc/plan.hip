@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 
 #include "mm_internal.h"
 #include "wave_runs.h"
@@ -295,11 +296,11 @@ template <class T>
 struct Scratch {
   T* p = nullptr;
   ~Scratch() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   }
   mm_status alloc(size_t n) {
     if (n == 0) n = 1;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&p), n * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
       return fail(MM_ERR_OOM, std::string("hipMalloc (plan scratch): ") + hipGetErrorString(e));
@@ -365,14 +366,104 @@ mm_status validate(const mm_geometry* g, std::vector<int>& order, int32_t& lambd
 
 }  // namespace
 
+std::shared_mutex& alloc_gate() {
+  static std::shared_mutex m;
+  return m;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  std::unique_lock<std::shared_mutex> lock(alloc_gate());
+  return hipMalloc(p, bytes);
+}
+
+void dev_free(void* p) {
+  if (p == nullptr) return;
+  std::unique_lock<std::shared_mutex> lock(alloc_gate());
+  (void)hipFree(p);
+}
+
+static bool needs_time_buffers(const Plan* P) {
+  return P->lambda_max > 0 && !(P->algo == MM_TOEPLITZ_FFT && P->fused);
+}
+
+static int32_t reduction_blocks(int64_t n_kept) {
+  int64_t nrb = (n_kept + 1023) / 1024;
+  return static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(nrb, 1), 1024));
+}
+
+int64_t work_bytes(const Plan* P) {
+  int64_t b = 0;
+  if (needs_time_buffers(P)) b += 2 * P->n_samples * static_cast<int64_t>(sizeof(float));
+  if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n))
+    b += static_cast<int64_t>(P->n_chunks) * (P->fft_n / 2) * static_cast<int64_t>(sizeof(float2));
+  b += 5 * 3 * P->n_kept * static_cast<int64_t>(sizeof(double));
+  b += 4 * static_cast<int64_t>(reduction_blocks(P->n_kept)) * sizeof(double);
+  b += sizeof(CgState);
+  return b;
+}
+
+mm_status work_alloc(const Plan* P, Work* W) {
+  *W = Work{};
+  struct Guard {
+    Work* w;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) work_free(w);
+    }
+  } guard{W};
+  auto get = [&](auto** ptr, size_t count) -> mm_status {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(*ptr)>>;
+    *ptr = nullptr;
+    if (count == 0) return MM_OK;
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
+    if (e != hipSuccess) {
+      *ptr = nullptr;
+      return fail(MM_ERR_OOM, std::string("hipMalloc (solve workspace): ") + hipGetErrorString(e));
+    }
+    W->bytes += static_cast<int64_t>(count * sizeof(T));
+    return MM_OK;
+  };
+  if (needs_time_buffers(P)) {
+    MM_TRY(get(&W->t, static_cast<size_t>(P->n_samples)));
+    MM_TRY(get(&W->u, static_cast<size_t>(P->n_samples)));
+  }
+  if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n))
+    MM_TRY(get(&W->scratch, static_cast<size_t>(P->n_chunks) * (P->fft_n / 2)));
+  const size_t nu = static_cast<size_t>(3 * P->n_kept);
+  MM_TRY(get(&W->r, nu));
+  MM_TRY(get(&W->z, nu));
+  MM_TRY(get(&W->p, nu));
+  MM_TRY(get(&W->q, nu));
+  MM_TRY(get(&W->b, nu));
+  W->nrb = reduction_blocks(P->n_kept);
+  MM_TRY(get(&W->partial, static_cast<size_t>(4 * W->nrb)));
+  MM_TRY(get(&W->state, 1));
+  {
+    std::unique_lock<std::shared_mutex> lock(alloc_gate());
+    MM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&W->h_state), sizeof(CgState),
+                             hipHostMallocDefault));
+  }
+  guard.keep = true;
+  return MM_OK;
+}
+
+void work_free(Work* W) {
+  void* ptrs[] = {W->t, W->u, W->scratch, W->r, W->z, W->p, W->q, W->b, W->partial, W->state};
+  for (void* p : ptrs) dev_free(p);
+  if (W->h_state) {
+    std::unique_lock<std::shared_mutex> lock(alloc_gate());
+    (void)hipHostFree(W->h_state);
+  }
+  *W = Work{};
+}
+
 void destroy_plan(Plan* P) {
   if (!P) return;
   void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
-                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->scratch, P->tiles, P->id_tiles, P->id_seg, P->t, P->u,
-                  P->r, P->z, P->p, P->q, P->b, P->partial, P->state};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (P->h_state) (void)hipHostFree(P->h_state);
+                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->tiles, P->id_tiles,
+                  P->id_seg};
+  for (void* p : ptrs) dev_free(p);
+  work_free(&P->work);
   if (P->aux) (void)hipStreamDestroy(P->aux);
   for (int k = 0; k < K_NKINDS; ++k)
     for (const TimedPair& t : P->timing.pending[k]) {
@@ -610,25 +701,10 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   }
 
   // ---- workspace -----------------------------------------------------------------------------
-  if (algo == MM_TOEPLITZ_FFT && long_fft_size(fft_n)) {
+  if (algo == MM_TOEPLITZ_FFT && long_fft_size(fft_n))
     P->fused = false;  // long segments: gather, four-step product and scatter as three kernels
-    MM_TRY(dalloc(P, &P->scratch, static_cast<size_t>(P->n_chunks) * (fft_n / 2)));
-  }
-  MM_TRY(dalloc(P, &P->t, n));
-  MM_TRY(dalloc(P, &P->u, n));
-  const int64_t nu = 3 * n_kept;
-  MM_TRY(dalloc(P, &P->r, nu));
-  MM_TRY(dalloc(P, &P->z, nu));
-  MM_TRY(dalloc(P, &P->p, nu));
-  MM_TRY(dalloc(P, &P->q, nu));
-  MM_TRY(dalloc(P, &P->b, nu));
-  int64_t nrb = (n_kept + 1023) / 1024;
-  if (nrb < 1) nrb = 1;
-  if (nrb > 1024) nrb = 1024;
-  P->n_red_blocks = static_cast<int32_t>(nrb);
-  MM_TRY(dalloc(P, &P->partial, 4 * nrb));
-  MM_TRY(dalloc(P, &P->state, 1));
-  MM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->h_state), sizeof(CgState), hipHostMallocDefault));
+  MM_TRY(work_alloc(P, &P->work));
+  P->device_bytes += P->work.bytes;
 
   unsigned long long h_gap = 0;
   MM_HIP_TRY(hipMemcpyAsync(&h_gap, ctr.p + 1, sizeof(h_gap), hipMemcpyDeviceToHost, s));

@@ -132,13 +132,13 @@ int32_t choose_fft_size(int32_t lambda_max) {
   return 0;
 }
 
-mm_status launch_noise_weight(Plan* P, const float* t, float* u, const int32_t* done,
-                              hipStream_t s) {
+mm_status launch_noise_weight(Plan* P, const float* t, float* u, float2* scratch,
+                              const int32_t* done, hipStream_t s) {
   if (P->n_samples == 0) return MM_OK;
   TimedLaunch tl(P, K_TOEPLITZ, s);
   if (P->n_chunks > 0) {
     if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n)) {
-      MM_TRY(launch_toeplitz_long(P, t, u, done, s));
+      MM_TRY(launch_toeplitz_long(P, t, u, scratch, done, s));
     } else if (P->algo == MM_TOEPLITZ_FFT) {
       switch (P->fft_n) {
         case 1 << 11: MM_TRY(launch_fft<10>(P, t, u, done, s)); break;

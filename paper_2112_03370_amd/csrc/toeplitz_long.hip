@@ -210,15 +210,16 @@ bool long_fft_size(int32_t n) { return n == (1 << 16) || n == (1 << 17); }
 
 int32_t long_fine_size() { return kFine; }
 
-mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, const int32_t* done,
-                               hipStream_t s) {
+mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, float2* scratch,
+                               const int32_t* done, hipStream_t s) {
   if (P->n_chunks == 0) return MM_OK;
+  if (scratch == nullptr) return fail(MM_ERR_INVALID, "long-segment product without its tiles");
   if (P->fft_n == (1 << 16)) {
     hipLaunchKernelGGL(k_toeplitz_long<15>, dim3(P->n_chunks), dim3(kLongThreads), 0, s, t, u,
-                       P->chunks, P->spec, P->tw0, P->tw1, P->scratch, P->lambda_max, done);
+                       P->chunks, P->spec, P->tw0, P->tw1, scratch, P->lambda_max, done);
   } else if (P->fft_n == (1 << 17)) {
     hipLaunchKernelGGL(k_toeplitz_long<16>, dim3(P->n_chunks), dim3(kLongThreads), 0, s, t, u,
-                       P->chunks, P->spec, P->tw0, P->tw1, P->scratch, P->lambda_max, done);
+                       P->chunks, P->spec, P->tw0, P->tw1, scratch, P->lambda_max, done);
   } else {
     return fail(MM_ERR_UNSUPPORTED, "long FFT size not supported");
   }

@@ -69,6 +69,28 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", _c_i64), ("n_slots", _c_i32), ("max_bypass", _c_i32)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("queued_ms", _c_dbl), ("run_ms", _c_dbl), ("total_ms", _c_dbl),
+                ("slot", _c_i32), ("pad", _c_i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("hbm_budget", _c_i64), ("bytes_in_use", _c_i64), ("peak_bytes", _c_i64),
+                ("submitted", _c_i64), ("completed", _c_i64), ("plan_hits", _c_i64),
+                ("plan_misses", _c_i64), ("evictions", _c_i64), ("queued", _c_i32),
+                ("running", _c_i32), ("peak_running", _c_i32), ("n_plans", _c_i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -96,6 +118,14 @@ def load(path: Optional[str] = None):
         "mm_pcg_solve": [_vp, _vp, _c_i32, _c_i64, _vp, P(SolveOpts), P(SolveInfo), _vp],
         "mm_set_timing": [_vp, _c_i32],
         "mm_kernel_time": [_vp, _c_i32, P(_c_dbl), P(_c_i64)],
+        "mm_server_create": [P(ServerOpts), P(_vp)],
+        "mm_server_destroy": [_vp],
+        "mm_server_plan": [_vp, P(Geometry), ctypes.c_uint64, P(PlanInfo)],
+        "mm_submit": [_vp, ctypes.c_uint64, _vp, _c_i32, _c_i64, _vp, P(SolveOpts),
+                      P(ctypes.c_uint64)],
+        "mm_poll": [_vp, ctypes.c_uint64, P(SolveInfo), P(RequestTimes)],
+        "mm_wait": [_vp, ctypes.c_uint64, P(SolveInfo), P(RequestTimes)],
+        "mm_server_stats": [_vp, P(ServerStats)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -129,52 +159,62 @@ def _host(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
+def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
+                  det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0, flags=0):
+    """mm_geometry for device pointing tensors and host tables; returns (Geometry, keep-alive
+    list of the host arrays it points into)."""
+    import torch
+    for name, t, dt in (("pix", pix, torch.int32), ("wq", wq, torch.float32),
+                        ("wu", wu, torch.float32)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA {dt} tensor")
+    n = int(pix.numel())
+    if wq.numel() != n or wu.numel() != n:
+        raise ValueError("pix, wq, wu sizes differ")
+    bs = _host(blk_start, np.int64)
+    bl = _host(blk_len, np.int64)
+    bb = _host(blk_band, np.int32)
+    ncoef = np.array([len(b) for b in bands], np.int32)
+    off = np.zeros(len(bands), np.int64)
+    if len(bands) > 1:
+        off[1:] = np.cumsum(ncoef[:-1])
+    coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
+            else np.zeros(1, np.float32))
+    coef = np.ascontiguousarray(coef, np.float32)
+    det = None if det_offset is None else _host(det_offset, np.int64)
+    g = Geometry()
+    g.n_samples = n
+    g.pix, g.w_q, g.w_u = _ptr(pix), _ptr(wq), _ptr(wu)
+    g.n_pix_global = int(n_pix_global)
+    g.n_blocks = len(bs)
+    g.blk_start = bs.ctypes.data
+    g.blk_len = bl.ctypes.data
+    g.blk_band = bb.ctypes.data
+    g.n_bands = len(bands)
+    g.band_ncoef = ncoef.ctypes.data
+    g.band_offset = off.ctypes.data
+    g.band_coef = coef.ctypes.data
+    g.n_dets = 0 if det is None else len(det) - 1
+    g.det_offset = None if det is None else det.ctypes.data
+    g.cond_max = float(cond_max)
+    g.toeplitz_algo = int(toeplitz_algo)
+    g.fft_size = int(fft_size)
+    g.flags = int(flags)
+    return g, [bs, bl, bb, ncoef, off, coef, det, pix, wq, wu]
+
+
 class Plan:
     """Device plan of one geometry.  Time-ordered inputs are torch CUDA tensors."""
 
     def __init__(self, pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
                  det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0,
                  flags=0, stream=None):
-        import torch
         lib = load()
         self._lib = lib
         self.device = pix.device
-        for name, t, dt in (("pix", pix, torch.int32), ("wq", wq, torch.float32),
-                            ("wu", wu, torch.float32)):
-            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
-                raise ValueError(f"{name} must be a contiguous CUDA {dt} tensor")
         n = int(pix.numel())
-        if wq.numel() != n or wu.numel() != n:
-            raise ValueError("pix, wq, wu sizes differ")
-        self._bs = _host(blk_start, np.int64)
-        self._bl = _host(blk_len, np.int64)
-        self._bb = _host(blk_band, np.int32)
-        ncoef = np.array([len(b) for b in bands], np.int32)
-        off = np.zeros(len(bands), np.int64)
-        if len(bands) > 1:
-            off[1:] = np.cumsum(ncoef[:-1])
-        coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
-                else np.zeros(1, np.float32))
-        self._nc, self._off, self._coef = ncoef, off, np.ascontiguousarray(coef, np.float32)
-        self._det = None if det_offset is None else _host(det_offset, np.int64)
-        g = Geometry()
-        g.n_samples = n
-        g.pix, g.w_q, g.w_u = _ptr(pix), _ptr(wq), _ptr(wu)
-        g.n_pix_global = int(n_pix_global)
-        g.n_blocks = len(self._bs)
-        g.blk_start = self._bs.ctypes.data
-        g.blk_len = self._bl.ctypes.data
-        g.blk_band = self._bb.ctypes.data
-        g.n_bands = len(bands)
-        g.band_ncoef = ncoef.ctypes.data
-        g.band_offset = off.ctypes.data
-        g.band_coef = self._coef.ctypes.data
-        g.n_dets = 0 if self._det is None else len(self._det) - 1
-        g.det_offset = None if self._det is None else self._det.ctypes.data
-        g.cond_max = float(cond_max)
-        g.toeplitz_algo = int(toeplitz_algo)
-        g.fft_size = int(fft_size)
-        g.flags = int(flags)
+        g, self._keep = make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band,
+                                      bands, det_offset, cond_max, toeplitz_algo, fft_size, flags)
         h = _vp()
         self._h = None
         check(lib.mm_plan(ctypes.byref(g), _stream(stream), ctypes.byref(h)))
@@ -297,3 +337,90 @@ def exported_symbols(header: Optional[str] = None) -> Sequence[str]:
         src = open(h).read()
         names += re.findall(r"^\s*(?:mm_status|const char\*)\s+(mm_\w+)\s*\(", src, re.M)
     return names
+
+
+class Server:
+    """Serving loop: device-cached plans and continuously batched solves (mm_server_*)."""
+
+    def __init__(self, hbm_budget=0, n_slots=4, max_bypass=-1):
+        self._lib = load()
+        o = ServerOpts(hbm_budget=int(hbm_budget), n_slots=int(n_slots),
+                       max_bypass=int(max_bypass))
+        h = _vp()
+        self._h = None
+        check(self._lib.mm_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h.value
+        self._inflight = {}   # ticket -> (d, x, k) kept alive until polled
+
+    def plan(self, key, pix=None, wq=None, wu=None, n_pix_global=0, blk_start=(), blk_len=(),
+             blk_band=(), bands=(), det_offset=None, **kw) -> dict:
+        """Make the plan of a geometry available under `key` (no geometry needed on a hit)."""
+        info = PlanInfo()
+        if pix is None:
+            check(self._lib.mm_server_plan(self._h, None, ctypes.c_uint64(key), ctypes.byref(info)))
+        else:
+            g, keep = make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band,
+                                    bands, det_offset, **kw)
+            check(self._lib.mm_server_plan(self._h, ctypes.byref(g), ctypes.c_uint64(key),
+                                           ctypes.byref(info)))
+            del keep
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def plan_from_problem(self, key, prob, device="cuda", **kw):
+        import torch
+        pix = torch.from_numpy(np.ascontiguousarray(prob.pix)).to(device)
+        wq = torch.from_numpy(np.ascontiguousarray(prob.wq)).to(device)
+        wu = torch.from_numpy(np.ascontiguousarray(prob.wu)).to(device)
+        return self.plan(key, pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                         prob.blk_band, prob.bands, det_offset=prob.det_offset, **kw)
+
+    def submit(self, key, d, x, tol=1e-8, max_iter=10000, block=0, use_graph=True,
+               check_every=0) -> int:
+        """Queue a solve of the rows of d (CUDA float32, [k, n] or [n]) into x (CUDA float64,
+        [k, n_kept, 3] or [n_kept, 3]); returns the ticket."""
+        k = 1 if d.dim() == 1 else int(d.shape[0])
+        ld = int(d.shape[-1])
+        o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=0, check_every=check_every,
+                      use_graph=int(use_graph), block=int(block))
+        t = ctypes.c_uint64()
+        check(self._lib.mm_submit(self._h, ctypes.c_uint64(key), _ptr(d), k, ld, _ptr(x),
+                                  ctypes.byref(o), ctypes.byref(t)))
+        self._inflight[t.value] = (d, x, k)
+        return t.value
+
+    def _finish(self, fn, ticket, raise_on_error):
+        d, x, k = self._inflight.get(ticket, (None, None, 1))
+        infos = (SolveInfo * max(1, k))()
+        times = RequestTimes()
+        st = fn(self._h, ctypes.c_uint64(ticket), infos, ctypes.byref(times))
+        if st == MM_PENDING:
+            return None
+        self._inflight.pop(ticket, None)
+        if raise_on_error:
+            check(st)
+        res = [infos[j].as_dict() for j in range(k)]
+        return {"status": STATUS.get(st, st), "info": res, "times": times.as_dict(), "x": x}
+
+    def poll(self, ticket, raise_on_error=True):
+        """None while pending, else a dict with status, per-column info, times and x."""
+        return self._finish(self._lib.mm_poll, ticket, raise_on_error)
+
+    def wait(self, ticket, raise_on_error=True):
+        return self._finish(self._lib.mm_wait, ticket, raise_on_error)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(self._lib.mm_server_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mm_server_destroy(self._h)
+            self._h = None
+            self._inflight.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

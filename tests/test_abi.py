@@ -34,6 +34,15 @@ def test_status_strings_without_device():
     # argument validation happens before any device call
     assert lib.mm_plan(None, None, None) == -1
     assert lib.mm_plan_destroy(None) == 0
+    # serving calls validate their handles before touching a device
+    assert lib.mm_server_create(None, None) == -1
+    assert lib.mm_server_destroy(None) == 0
+    t = ctypes.c_uint64()
+    assert lib.mm_submit(None, 1, None, 1, 0, None, None, ctypes.byref(t)) == -1
+    assert lib.mm_poll(None, 1, None, None) == -1
+    assert lib.mm_wait(None, 1, None, None) == -1
+    assert lib.mm_server_stats(None, None) == -1
+    assert lib.mm_server_plan(None, None, 1, None) == -1
 
 
 def test_struct_layout_matches_header():
@@ -52,6 +61,11 @@ int main(void) {
   P(mm_plan_info_t, n_chunks) P(mm_plan_info_t, fused)
   P(mm_solve_info, relres) P(mm_solve_info, ms) P(mm_solve_opts, use_graph)
   P(mm_solve_opts, block) P(mm_solve_info, block)
+  printf("mm_server_opts %zu\n", sizeof(mm_server_opts));
+  printf("mm_request_times %zu\n", sizeof(mm_request_times));
+  printf("mm_server_stats_t %zu\n", sizeof(mm_server_stats_t));
+  P(mm_server_opts, max_bypass) P(mm_request_times, slot) P(mm_server_stats_t, queued)
+  P(mm_server_stats_t, n_plans)
   return 0;
 }
 """
@@ -80,5 +94,12 @@ int main(void) {
         "mm_solve_opts.use_graph": M.SolveOpts.use_graph.offset,
         "mm_solve_opts.block": M.SolveOpts.block.offset,
         "mm_solve_info.block": M.SolveInfo.block.offset,
+        "mm_server_opts": ctypes.sizeof(M.ServerOpts),
+        "mm_request_times": ctypes.sizeof(M.RequestTimes),
+        "mm_server_stats_t": ctypes.sizeof(M.ServerStats),
+        "mm_server_opts.max_bypass": M.ServerOpts.max_bypass.offset,
+        "mm_request_times.slot": M.RequestTimes.slot.offset,
+        "mm_server_stats_t.queued": M.ServerStats.queued.offset,
+        "mm_server_stats_t.n_plans": M.ServerStats.n_plans.offset,
     }
     assert {k: int(v) for k, v in got.items()} == exp
