@@ -38,6 +38,9 @@ WORKLOADS = {
                  "pixels, HWP, lambda 32768, f_knee 0.05 Hz",
     "batched": "batched multi-RHS: ground-like 64 det x 2^20 samples (67,108,864), intervals "
                "2^16, 512x512 patch, lambda 8192, 64 right-hand sides sharing P and N^-1",
+    "serving": "serving: 400 requests, Poisson arrivals at 0.8x the sequential capacity, Zipf(1.1) "
+               "over 24 ground-like geometries (4-32 det x 2^16-2^18 samples, 32^2-128^2 patches, "
+               "lambda 2^8-2^13), 1-4 RHS per request",
 }
 
 
@@ -237,6 +240,209 @@ def run_batched(args, prob, mm, torch, dev, stream):
     }
 
 
+def run_serving(args, mm, torch, dev):
+    """Continuous batching: the same request trace served by the server (n_slots solves at
+    once, plans cached on the device) and by plain per-request PCG run one at a time, both
+    saturated (all requests at once: capacity) and under Poisson arrivals at 0.8x the
+    sequential capacity (latency from arrival to result)."""
+    import threading
+
+    import synth
+    t0 = time.time()
+    pool = synth.serving_pool()
+    geom, ks, gaps = synth.serving_trace()
+    n_req = len(geom)
+    log(f"[bench] serving pool of {len(pool)} geometries, {n_req} requests, "
+        f"generated in {time.time() - t0:.1f} s")
+    dev_in = []
+    for p in pool:
+        dev_in.append(dict(pix=torch.from_numpy(p.pix).to(dev), wq=torch.from_numpy(p.wq).to(dev),
+                           wu=torch.from_numpy(p.wu).to(dev), d=torch.from_numpy(p.d).to(dev)))
+    geoms = [mm.make_geometry(di["pix"], di["wq"], di["wu"], p.n_pix_global, p.blk_start,
+                              p.blk_len, p.blk_band, p.bands, p.det_offset)
+             for p, di in zip(pool, dev_in)]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream(device=dev)
+
+    # plans once, for sizes; outputs for both runs allocated up front (inputs and outputs are
+    # resident before any timed region)
+    n_kept = []
+    for gi, p in enumerate(pool):
+        with torch.cuda.stream(stream):
+            pl = mm.Plan(dev_in[gi]["pix"], dev_in[gi]["wq"], dev_in[gi]["wu"], p.n_pix_global,
+                         p.blk_start, p.blk_len, p.blk_band, p.bands, det_offset=p.det_offset,
+                         stream=stream)
+        n_kept.append(pl.n_kept)
+        pl.close()
+    x_seq = [torch.empty((int(ks[i]), n_kept[geom[i]], 3), dtype=torch.float64, device=dev)
+             for i in range(n_req)]
+    x_srv = [torch.empty_like(x) for x in x_seq]
+    work = sum(pool[geom[i]].n_samples * int(ks[i]) for i in range(n_req))
+
+    def sequential(arrivals):
+        plans = {}
+        lat, iters = [], 0
+        t_start = time.perf_counter()
+        for i in range(n_req):
+            if arrivals is not None:
+                t_arr = t_start + arrivals[i]
+                while time.perf_counter() < t_arr:
+                    time.sleep(min(1e-3, max(0.0, t_arr - time.perf_counter())))
+            else:
+                t_arr = t_start
+            gi = int(geom[i])
+            with torch.cuda.stream(stream):
+                if gi not in plans:
+                    p, di = pool[gi], dev_in[gi]
+                    plans[gi] = mm.Plan(di["pix"], di["wq"], di["wu"], p.n_pix_global,
+                                        p.blk_start, p.blk_len, p.blk_band, p.bands,
+                                        det_offset=p.det_offset, stream=stream)
+                k = int(ks[i])
+                _, info = plans[gi].pcg_solve(dev_in[gi]["d"][:k], x=x_seq[i], tol=args.tol,
+                                              stream=stream)
+            infos = info if isinstance(info, list) else [info]
+            iters += sum(int(f["iterations"]) for f in infos)
+            lat.append(1e3 * (time.perf_counter() - t_arr))
+        total = time.perf_counter() - t_start
+        for pl in plans.values():
+            pl.close()
+        return total, np.array(lat), iters
+
+    def served(arrivals, n_slots):
+        srv = mm.Server(n_slots=n_slots)
+        t_arr = np.zeros(n_req)
+        t_sub = np.zeros(n_req)
+        tickets = [None] * n_req
+        err = []
+        t_start = time.perf_counter()
+
+        def submitter():
+            try:
+                for i in range(n_req):
+                    if arrivals is not None:
+                        ta = t_start + arrivals[i]
+                        while time.perf_counter() < ta:
+                            time.sleep(min(1e-3, max(0.0, ta - time.perf_counter())))
+                    t_arr[i] = time.perf_counter()
+                    gi = int(geom[i])
+                    srv.plan(gi + 1, geometry=geoms[gi][0])
+                    k = int(ks[i])
+                    tickets[i] = srv.submit(gi + 1, dev_in[gi]["d"][:k], x_srv[i], tol=args.tol)
+                    t_sub[i] = time.perf_counter()
+            except Exception as ex:  # reported by the main thread
+                err.append(ex)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat = np.zeros(n_req)
+        iters = 0
+        samp_iters = 0
+        for i in range(n_req):
+            while tickets[i] is None and not err:
+                time.sleep(2e-4)
+            if err:
+                break
+            res = srv.wait(tickets[i])
+            iters += sum(int(f["iterations"]) for f in res["info"])
+            # products per column: the iterations, the right-hand side and the true residual
+            samp_iters += pool[geom[i]].n_samples * sum(int(f["iterations"]) + 2
+                                                        for f in res["info"])
+            lat[i] = 1e3 * (t_sub[i] - t_arr[i]) + res["times"]["total_ms"]
+        th.join()
+        if err:
+            raise err[0]
+        st = srv.stats()
+        done_t = time.perf_counter()
+        srv.close()
+        return done_t - t_start, lat, iters, st, samp_iters
+
+    # warm-up: one pass of each geometry through both paths (plan builds, graph code paths)
+    for gi in range(len(pool)):
+        with torch.cuda.stream(stream):
+            p, di = pool[gi], dev_in[gi]
+            pl = mm.Plan(di["pix"], di["wq"], di["wu"], p.n_pix_global, p.blk_start, p.blk_len,
+                         p.blk_band, p.bands, det_offset=p.det_offset, stream=stream)
+            pl.pcg_solve(di["d"][:1], tol=args.tol, stream=stream)
+            pl.close()
+    torch.cuda.synchronize()
+
+    t_seq, lat_seq_sat, it_seq = sequential(None)
+    cap_seq = n_req / t_seq
+    log(f"[bench] sequential, saturated: {t_seq:.2f} s, {cap_seq:.1f} requests/s")
+    t_srv, lat_srv_sat, it_srv, st_sat, samp_srv = served(None, args.slots)
+    log(f"[bench] served ({args.slots} slots), saturated: {t_srv:.2f} s, "
+        f"{n_req / t_srv:.1f} requests/s, peak running {st_sat['peak_running']}")
+    # same results alone and in the mix
+    diffs = [float((a - b).norm() / b.norm().clamp_min(1e-300)) for a, b in zip(x_srv, x_seq)]
+    max_diff = max(diffs)
+    rate = args.load * cap_seq
+    arrivals = np.cumsum(gaps) / rate
+    t_seq_p, lat_seq, _ = sequential(arrivals)
+    t_srv_p, lat_srv, _, st_p, _ = served(arrivals, args.slots)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3)  # noqa: E731
+    log(f"[bench] Poisson at {rate:.1f} requests/s: sequential p50 {pct(lat_seq, 50)} ms p99 "
+        f"{pct(lat_seq, 99)} ms; served p50 {pct(lat_srv, 50)} ms p99 {pct(lat_srv, 99)} ms; "
+        f"max map rel diff mix vs alone {max_diff:.2e}")
+    n_rhs = int(ks.sum())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        n_done, rhs_done = 0, 0
+        refs = {}
+        while n_done < n_req and time.perf_counter() - t0 < 15.0:
+            gi = int(geom[n_done])
+            if gi not in refs:
+                refs[gi] = O.plan_from_problem(pool[gi])
+            for j in range(int(ks[n_done])):
+                O.pcg(refs[gi], O.rhs(refs[gi], pool[gi].d[j]), tol=args.tol)
+                rhs_done += 1
+            n_done += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": rhs_done / dt, "unit": "RHS solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_done} requests of the trace ({rhs_done} RHS, plans included) "
+                         f"solved one by one in {dt:.1f} s; scipy.fft workers={threads}"}
+        log(f"[bench] cpu baseline {cpu['value']:.3f} RHS solves/s")
+
+    # aggregate rate of the served saturated run against the HBM roofline: the fused product
+    # reads 12 B of pointing per sample and product; kernels of several requests overlap, so
+    # this is the work of the whole run over its wall time
+    agg = 12.0 * samp_srv / t_srv / 1e9
+    return {
+        "metric": "served p50/p99 latency at rel-res 1e-8",
+        "value": pct(lat_srv, 99),
+        "unit": "ms (p99, arrival to result)",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1e3 * t_srv_p, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 time-domain / f64 pixel-domain",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["serving"], "requests": n_req, "rhs": n_rhs,
+                   "tod_samples_x_rhs": work, "slots": args.slots, "load": args.load,
+                   "arrival_rate_per_s": round(rate, 3), "tol": args.tol,
+                   "parallelism": "single GPU"},
+        "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99),
+                   "saturated_requests_per_s": round(n_req / t_srv, 3),
+                   "saturated_rhs_solves_per_s": round(n_rhs / t_srv, 3),
+                   "peak_running": st_sat["peak_running"], "plan_hits": st_p["plan_hits"],
+                   "plan_misses": st_p["plan_misses"],
+                   "peak_device_bytes": st_sat["peak_bytes"]},
+        "sequential": {"p50_ms": pct(lat_seq, 50), "p99_ms": pct(lat_seq, 99),
+                       "saturated_requests_per_s": round(cap_seq, 3),
+                       "saturated_rhs_solves_per_s": round(n_rhs / t_seq, 3)},
+        "speedup_saturated": round(t_seq / t_srv, 3),
+        "max_map_rel_diff_mix_vs_alone": max_diff,
+        "iterations_total": int(it_srv),
+        "roofline": {"bound": "hbm", "achieved": round(agg, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(agg / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "apply_fused, aggregate over overlapping requests",
+                     "tod_sample_products": int(samp_srv)},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +455,9 @@ def main():
                     help="three-kernel FFT path (gather / Toeplitz / scatter) instead of fused")
     ap.add_argument("--block", type=int, default=-1,
                     help="batched workload: right-hand sides per block (-1: tuned among 8/16/32)")
+    ap.add_argument("--slots", type=int, default=8, help="serving workload: solves at once")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving workload: Poisson rate as a fraction of sequential capacity")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for PMC scaling)")
     args = ap.parse_args()
@@ -263,6 +472,9 @@ def main():
     mm.load()
     assert torch.cuda.is_available(), "no GPU"
     dev = torch.device("cuda:0")
+    if args.config == "serving":
+        print(json.dumps(run_serving(args, mm, torch, dev)), flush=True)
+        return
     t0 = time.time()
     prob = make_workload(args.config)
     log(f"[bench] generated {args.config}: {prob.n_samples} samples in {time.time() - t0:.1f} s")

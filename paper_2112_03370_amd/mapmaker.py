@@ -353,10 +353,14 @@ class Server:
         self._inflight = {}   # ticket -> (d, x, k) kept alive until polled
 
     def plan(self, key, pix=None, wq=None, wu=None, n_pix_global=0, blk_start=(), blk_len=(),
-             blk_band=(), bands=(), det_offset=None, **kw) -> dict:
-        """Make the plan of a geometry available under `key` (no geometry needed on a hit)."""
+             blk_band=(), bands=(), det_offset=None, geometry=None, **kw) -> dict:
+        """Make the plan of a geometry available under `key` (no geometry needed on a hit;
+        `geometry` may be a prepared Geometry from make_geometry)."""
         info = PlanInfo()
-        if pix is None:
+        if geometry is not None:
+            check(self._lib.mm_server_plan(self._h, ctypes.byref(geometry), ctypes.c_uint64(key),
+                                           ctypes.byref(info)))
+        elif pix is None:
             check(self._lib.mm_server_plan(self._h, None, ctypes.c_uint64(key), ctypes.byref(info)))
         else:
             g, keep = make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band,

@@ -13,6 +13,8 @@ from .problems import (  # noqa: F401
     make_satellite,
     make_random_small,
     make_config,
+    serving_pool,
+    serving_trace,
     inverse_noise_band,
     noise_psd,
     CONFIGS,

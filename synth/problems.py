@@ -7,6 +7,7 @@ can be regenerated independently of the others.  Streams:
     3 knee frequencies            4 noise, keyed by (detector, interval, rhs)
     5 sky maps, keyed by rhs      6 per-sweep boresight rotation
     7 flagged samples             8 random block layouts (small random problems)
+    9 serving workload: geometry sizes and the request trace
 
 Data model (Eq. dataModelSingleSlot / Eq. dataModelHwp): d_t = I_p + cos(2psi_t) Q_p +
 sin(2psi_t) U_p + n_t, with p = p(t).  The per-sample weights are stored as FP32 and *define* the
@@ -34,7 +35,7 @@ import scipy.fft as sfft
 
 MASTER_SEED = 211203370
 
-_S_OFFSETS, _S_PSI, _S_FKNEE, _S_NOISE, _S_SKY, _S_RHO, _S_FLAGS, _S_LAYOUT = range(1, 9)
+_S_OFFSETS, _S_PSI, _S_FKNEE, _S_NOISE, _S_SKY, _S_RHO, _S_FLAGS, _S_LAYOUT, _S_TRACE = range(1, 10)
 
 
 def _rng(cfg_id: int, stream: int, *keys: int) -> np.random.Generator:
@@ -464,6 +465,38 @@ CONFIGS = {
                     interval=1 << 16, side=512, dwell=16, lam=8192, fknee_range=(0.1, 2.0),
                     fsample=100.0, n_rhs=64),
 }
+
+
+def serving_pool(cfg_id=4, n_geoms=24, dets=(4, 32), log2_samples=(16, 18), sides=(32, 128),
+                 log2_lam=(8, 13), n_rhs=4, interval=1 << 16):
+    """Geometries of the serving workload: ground-like sweeps of uneven size, one draw per
+    geometry of detectors ~ U{dets}, samples per detector 2^e with e ~ U{log2_samples}, patch
+    side ~ U{sides}, half-bandwidth 2^g with g ~ U{log2_lam}; n_rhs data realizations each.
+    Geometry i uses the streams of configuration 100 cfg_id + i."""
+    g = _rng(cfg_id, _S_TRACE, 0)
+    pool = []
+    for i in range(n_geoms):
+        nd = int(g.integers(dets[0], dets[1] + 1))
+        e = int(g.integers(log2_samples[0], log2_samples[1] + 1))
+        side = int(g.integers(sides[0], sides[1] + 1))
+        lam = 1 << int(g.integers(log2_lam[0], log2_lam[1] + 1))
+        pool.append(make_ground(cfg_id=100 * cfg_id + i, n_dets=nd, samples_per_det=1 << e,
+                                interval=interval, side=side, dwell=16, lam=lam, n_rhs=n_rhs,
+                                name=f"serving-{i}"))
+    return pool
+
+
+def serving_trace(cfg_id=4, n_requests=400, n_geoms=24, zipf_s=1.1, k_range=(1, 4)):
+    """Request trace: geometry index by Zipf(zipf_s) popularity over the pool, right-hand sides
+    per request ~ U{k_range}, and unit-rate exponential inter-arrival gaps (Poisson arrivals;
+    divide by the rate)."""
+    g = _rng(cfg_id, _S_TRACE, 1)
+    p = 1.0 / np.arange(1, n_geoms + 1) ** zipf_s
+    p /= p.sum()
+    geom = g.choice(n_geoms, size=n_requests, p=p)
+    k = g.integers(k_range[0], k_range[1] + 1, size=n_requests)
+    gaps = g.exponential(1.0, size=n_requests)
+    return geom.astype(np.int64), k.astype(np.int64), gaps
 
 
 def make_config(name, **overrides):
