@@ -17,6 +17,13 @@ Readings where the paper is silent (each also listed in the design notes):
   * a pixel is kept when it has >= 3 hits and its 3x3 BJ block has condition number <= cond_max
     (default 1e3; the paper sets a threshold without a value);
   * a zero right-hand side (or an exactly converged start) returns after 0 iterations.
+
+Two-level a posteriori preconditioner (Eq. 2lvlDef, A-DEF1; Alg. 3):
+  * Lanczos runs on A itself (not on M_BD A), from r0 = b (x0 = 0), storing V_m and A V_m;
+  * the deflation space takes all m Ritz vectors Z = V_m X of the tridiagonal T_m = X Theta X^T,
+    with Z' = (A V_m) X and E = Z^T Z' formed explicitly, as the paper does;
+  * E^-1 is a pseudo-inverse (the paper uses a least-squares SVD solver): E is symmetrized and
+    its eigen-directions with eigenvalues <= 1e-12 of the largest are dropped.
 """
 
 from __future__ import annotations
@@ -35,7 +42,8 @@ __all__ = [
     "noise_weight_fft", "noise_weight", "unpoint", "point", "rhs", "apply_A", "precond_bj",
     "PCGResult", "pcg", "lanczos_extremes", "binned_map", "dense_pointing",
     "dense_noise_inverse", "dense_A", "solve_dense", "default_fft_size", "block_pcg",
-    "BlockPCGResult", "block_ecg", "sym_pinv",
+    "BlockPCGResult", "block_ecg", "sym_pinv", "LanczosResult", "lanczos", "Deflation",
+    "deflation_from_lanczos", "precond_2lvl",
 ]
 
 DEFAULT_COND_MAX = 1.0e3
@@ -519,3 +527,100 @@ def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=
         active = active[keep]
     relres = np.where(nb > 0, np.linalg.norm(R, axis=1) / np.where(nb > 0, nb, 1.0), 0.0)
     return BlockPCGResult(X.reshape(B.shape), iters, relres, conv, k)
+
+
+# --------------------------------------------------------------------------------------------
+# Two-level a posteriori preconditioner (Eq. 2lvlDef, Alg. 3)
+# --------------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class LanczosResult:
+    alpha: np.ndarray        # [m] diagonal of T_m
+    beta: np.ndarray         # [m + 1]: beta[0] = ||r0||, beta[k] couples v_k and v_(k+1)
+    V: np.ndarray            # [m, n_kept, 3] Lanczos vectors v_1..v_m
+    AV: np.ndarray           # [m, n_kept, 3] the stored products A v_k
+    v_next: np.ndarray       # v_(m+1) (zero when the process stopped on beta < eps)
+    m: int
+
+    def T(self):
+        """The tridiagonal T_m = tridiag(beta_i, alpha_i, beta_(i+1))."""
+        m = self.m
+        t = np.diag(self.alpha[:m])
+        if m > 1:
+            off = self.beta[1:m]
+            t += np.diag(off, 1) + np.diag(off, -1)
+        return t
+
+
+def lanczos(plan, r0, m, apply=None, eps=None):
+    """Alg. 3 on A from the start vector r0 (= b - A x0; r0 = b for x0 = 0): v_1 = r0/||r0||;
+    per step w = A v_k - beta_k v_(k-1) (A v_k stored), alpha_k = <w, v_k>, w -= alpha_k v_k,
+    beta_(k+1) = ||w||, stop when beta_(k+1) < eps, else v_(k+1) = w / beta_(k+1).  eps defaults
+    to machine precision times ||r0||."""
+    A = apply or (lambda v: apply_A(plan, v))
+    r0 = np.asarray(r0, np.float64).reshape(-1, 3)
+    b1 = float(np.linalg.norm(r0))
+    if eps is None:
+        eps = np.finfo(np.float64).eps * max(b1, 1.0)
+    alpha = np.zeros(m)
+    beta = np.zeros(m + 1)
+    beta[0] = b1
+    V = np.zeros((m,) + r0.shape)
+    AV = np.zeros((m,) + r0.shape)
+    if b1 == 0.0:
+        return LanczosResult(alpha[:0], beta[:1], V[:0], AV[:0], np.zeros_like(r0), 0)
+    v = r0 / b1
+    v_prev = np.zeros_like(r0)
+    k_done = m
+    v_next = np.zeros_like(r0)
+    for k in range(m):
+        V[k] = v
+        av = A(v)
+        AV[k] = av
+        w = av - (beta[k] * v_prev if k > 0 else 0.0)
+        alpha[k] = float(np.sum(w * v))
+        w = w - alpha[k] * v
+        beta[k + 1] = float(np.linalg.norm(w))
+        if beta[k + 1] < eps:
+            k_done = k + 1
+            v_next = np.zeros_like(r0)
+            break
+        v_prev, v = v, w / beta[k + 1]
+        v_next = v
+    return LanczosResult(alpha[:k_done], beta[:k_done + 1], V[:k_done], AV[:k_done], v_next,
+                         k_done)
+
+
+@dataclasses.dataclass
+class Deflation:
+    Z: np.ndarray            # [dim, n_kept, 3] deflation vectors
+    Zp: np.ndarray           # [dim, n_kept, 3] Z' = A Z
+    E: np.ndarray            # [dim, dim] coarse matrix Z^T A Z (= Z^T Z')
+    Einv: np.ndarray         # pseudo-inverse of E
+    theta: np.ndarray        # Ritz values of T_m
+
+
+def deflation_from_lanczos(lz, rtol=1e-12):
+    """Ritz pairs of T_m give Z = V_m X and Z' = (A V_m) X; the coarse matrix E = Z^T Z' and its
+    pseudo-inverse complete the preconditioner (2lvl a posteriori construction)."""
+    theta, X = np.linalg.eigh(lz.T())
+    m = lz.m
+    Vf = lz.V.reshape(m, -1)
+    AVf = lz.AV.reshape(m, -1)
+    Z = X.T @ Vf                 # row j = sum_i X[i, j] v_i
+    Zp = X.T @ AVf
+    E = Z @ Zp.T
+    Einv = sym_pinv(0.5 * (E + E.T), rtol)
+    shape = (m,) + lz.V.shape[1:]
+    return Deflation(Z.reshape(shape), Zp.reshape(shape), E, Einv, theta)
+
+
+def precond_2lvl(plan, defl, r):
+    """Eq. 2lvlDef0: M_2lvl r = M_BD r - M_BD Z' E^-1 Z^T r + Z E^-1 Z^T r, applied factor by
+    factor from the right."""
+    r = np.asarray(r, np.float64).reshape(-1, 3)
+    dim = defl.Z.shape[0]
+    Zf = defl.Z.reshape(dim, -1)
+    Zpf = defl.Zp.reshape(dim, -1)
+    c = defl.Einv @ (Zf @ r.reshape(-1))
+    return precond_bj(plan, r - (Zpf.T @ c).reshape(-1, 3)) + (Zf.T @ c).reshape(-1, 3)

@@ -401,3 +401,97 @@ def test_sym_pinv_drops_null_directions():
     G = (V * w) @ V.T
     want = (V[:, :3] / w[:3]) @ V[:, :3].T
     np.testing.assert_allclose(O.sym_pinv(G), want, atol=1e-10)
+
+
+# ------------------------------------------------------------------------------------------
+# Two-level a posteriori preconditioner (Eq. 2lvlDef, Alg. 3)
+# ------------------------------------------------------------------------------------------
+
+def _dense_A(plan):
+    n = 3 * plan.n_kept
+    return np.array([O.apply_A(plan, e.reshape(-1, 3), "direct").reshape(-1)
+                     for e in np.eye(n)]).T
+
+
+def test_lanczos_relation_and_orthonormal_basis():
+    _, plan, B = _stack(3, 1)
+    lz = O.lanczos(plan, B[0], 12, apply=lambda v: O.apply_A(plan, v, "direct"))
+    V = lz.V.reshape(lz.m, -1).T
+    AV = lz.AV.reshape(lz.m, -1).T
+    A = _dense_A(plan)
+    # the stored products are A v_k, and A V_m = V_m T_m + beta_(m+1) v_(m+1) e_m^T
+    np.testing.assert_allclose(AV, A @ V, atol=1e-12 * np.abs(AV).max())
+    resid = AV - V @ lz.T()
+    resid[:, -1] -= lz.beta[lz.m] * lz.v_next.reshape(-1)
+    assert np.abs(resid).max() <= 1e-12 * np.abs(AV).max()
+    assert np.abs(V.T @ V - np.eye(lz.m)).max() < 1e-10
+    np.testing.assert_allclose(V[:, 0], B[0].reshape(-1) / np.linalg.norm(B[0]), atol=1e-15)
+
+
+def test_lanczos_ritz_values_inside_and_converging_to_spectrum():
+    _, plan, B = _stack(4, 1)
+    A = _dense_A(plan)
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+    lz = O.lanczos(plan, B[0], 60, apply=lambda v: O.apply_A(plan, v, "direct"))
+    theta = np.linalg.eigvalsh(lz.T())
+    assert theta[0] >= ev[0] * (1 - 1e-9) and theta[-1] <= ev[-1] * (1 + 1e-9)
+    assert abs(theta[-1] - ev[-1]) / ev[-1] < 1e-8
+
+
+def _deflation_from_Z(plan, Z, apply):
+    Zp = np.stack([apply(z) for z in Z])
+    E = Z.reshape(len(Z), -1) @ Zp.reshape(len(Z), -1).T
+    return O.Deflation(Z, Zp, E, O.sym_pinv(0.5 * (E + E.T)), np.zeros(len(Z)))
+
+
+def test_2lvl_maps_deflation_space_to_itself():
+    # A-DEF1: (I - A Q) A Z = 0, so M_2lvl A Z = Q A Z = Z for any full-rank Z
+    _, plan, _ = _stack(5, 1)
+    apply = lambda v: O.apply_A(plan, v, "direct")  # noqa: E731
+    Z = np.random.default_rng(5).standard_normal((7, plan.n_kept, 3))
+    df = _deflation_from_Z(plan, Z, apply)
+    for j in range(7):
+        got = O.precond_2lvl(plan, df, apply(Z[j]))
+        np.testing.assert_allclose(got, Z[j], atol=1e-9 * np.abs(Z[j]).max())
+
+
+def test_2lvl_with_full_eigenbasis_is_the_inverse():
+    _, plan, B = _stack(6, 1)
+    apply = lambda v: O.apply_A(plan, v, "direct")  # noqa: E731
+    A = _dense_A(plan)
+    _, U = np.linalg.eigh(0.5 * (A + A.T))
+    Z = U.T.reshape(-1, plan.n_kept, 3)
+    df = _deflation_from_Z(plan, Z, apply)
+    res = O.pcg(plan, B[0], tol=1e-10, apply=apply, precond=lambda r: O.precond_2lvl(plan, df, r))
+    assert res.converged and res.iterations == 1
+    xs = np.linalg.solve(A, B[0].reshape(-1))
+    assert np.linalg.norm(res.x.reshape(-1) - xs) / np.linalg.norm(xs) < 1e-9
+
+
+def test_2lvl_pcg_solves_the_system():
+    prob, plan, B = _stack(7, 3)
+    apply = lambda v: O.apply_A(plan, v, "direct")  # noqa: E731
+    A = _dense_A(plan)
+    kappa = np.linalg.cond(A)
+    df = O.deflation_from_lanczos(O.lanczos(plan, B[0], 24, apply=apply))
+    assert df.Z.shape[0] == 24
+    for j in range(3):
+        bd = O.pcg(plan, B[j], tol=1e-10, apply=apply)
+        tl = O.pcg(plan, B[j], tol=1e-10, apply=apply,
+                   precond=lambda r: O.precond_2lvl(plan, df, r))
+        xs = np.linalg.solve(A, B[j].reshape(-1))
+        assert tl.converged and np.linalg.norm(tl.x.reshape(-1) - xs) / np.linalg.norm(xs) <= kappa * 1e-10
+        assert tl.iterations <= bd.iterations
+    # the start vector's own system gains most: its Krylov space is the one already built
+    own = O.pcg(plan, B[0], tol=1e-10, apply=apply, precond=lambda r: O.precond_2lvl(plan, df, r))
+    assert own.iterations <= O.pcg(plan, B[0], tol=1e-10, apply=apply).iterations // 2
+
+
+def test_2lvl_planted_swap_of_Z_and_AZ_is_caught():
+    _, plan, _ = _stack(5, 1)
+    apply = lambda v: O.apply_A(plan, v, "direct")  # noqa: E731
+    Z = np.random.default_rng(8).standard_normal((5, plan.n_kept, 3))
+    df = _deflation_from_Z(plan, Z, apply)
+    bad = O.Deflation(df.Zp, df.Z, df.E, df.Einv, df.theta)
+    got = O.precond_2lvl(plan, bad, apply(Z[0]))
+    assert np.abs(got - Z[0]).max() > 1e-3 * np.abs(Z[0]).max()
