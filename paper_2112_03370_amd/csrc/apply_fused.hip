@@ -6,19 +6,29 @@
 //
 // so the time-domain vectors never go to HBM: per output sample the kernel reads the pointing
 // of its input window (12 B per window sample, the lambda halo included) and again for its
-// outputs, and issues the run-merged atomics.  Segments are independent, so while some
-// workgroups stream pointing data others run their transforms, overlapping memory and VALU
-// work across the chip.  Samples outside every block (identity rows of stbmm) are handled by
-// the diagonal kernel over identity tiles.
+// outputs, and issues the run-merged atomics.  Samples outside every block (identity rows of
+// stbmm) are handled by the diagonal kernel over identity tiles.
+//
+// The gather is bound by the number of vector memory instructions, not by bytes: a lane takes
+// 8 consecutive samples (two 16-byte loads per pointing array) and loads a pixel's three values
+// only when the pixel changes, which scan runs make rare.
 #include "fft_lds.h"
 #include "mm_internal.h"
 #include "wave_runs.h"
+
+
 
 namespace mm {
 
 namespace {
 
 using namespace fft;
+
+// Consecutive samples per lane in the gather and in the scatter.  Wider lanes issue fewer,
+// wider memory instructions and load a pixel's values once per run; 8 is the widest that
+// 1,024-thread workgroups (128 registers per lane) hold without spilling.
+constexpr int kGatherLane = 8;
+constexpr int kScatterLane = 8;
 
 struct AtomicFlush {
   double* y;
@@ -39,6 +49,62 @@ __device__ __forceinline__ float gather_one(int key, float q, float w, const dou
   } else {
     const double* m = x + 3 * static_cast<int64_t>(key);
     return static_cast<float>(m[0] + static_cast<double>(q) * m[1] + static_cast<double>(w) * m[2]);
+  }
+}
+
+// Window samples [g, g + S) of one lane, inside the block and 16-byte aligned.  Scan runs keep
+// a pixel for several consecutive samples, so the lane loads a pixel's three values only when
+// the pixel changes from its previous sample (usually once or twice per lane) instead of once
+// per sample.
+template <int S, bool kFromData>
+__device__ __forceinline__ void gather_lane(const int32_t* __restrict__ lpix,
+                                            const float* __restrict__ wq,
+                                            const float* __restrict__ wu,
+                                            const double* __restrict__ x,
+                                            const float* __restrict__ d, int64_t g, float (&v)[S]) {
+  int kk[S];
+  float qq[S], uu[S];
+#pragma unroll
+  for (int c = 0; c < S / 4; ++c) {
+    const int4 k4 = *reinterpret_cast<const int4*>(lpix + g + 4 * c);
+    kk[4 * c] = k4.x;
+    kk[4 * c + 1] = k4.y;
+    kk[4 * c + 2] = k4.z;
+    kk[4 * c + 3] = k4.w;
+    // qq holds the data when gathering d, the weights otherwise
+    const float4 q4 = *reinterpret_cast<const float4*>((kFromData ? d : wq) + g + 4 * c);
+    qq[4 * c] = q4.x;
+    qq[4 * c + 1] = q4.y;
+    qq[4 * c + 2] = q4.z;
+    qq[4 * c + 3] = q4.w;
+    if constexpr (!kFromData) {
+      const float4 u4 = *reinterpret_cast<const float4*>(wu + g + 4 * c);
+      uu[4 * c] = u4.x;
+      uu[4 * c + 1] = u4.y;
+      uu[4 * c + 2] = u4.z;
+      uu[4 * c + 3] = u4.w;
+    }
+  }
+  if constexpr (kFromData) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) v[j] = kk[j] < 0 ? 0.0f : qq[j];
+  } else {
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    int cur = -1;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int key = kk[j];
+      if (key >= 0 && key != cur) {
+        const double* m = x + 3 * static_cast<int64_t>(key);
+        m0 = m[0];
+        m1 = m[1];
+        m2 = m[2];
+        cur = key;
+      }
+      v[j] = key < 0 ? 0.0f
+                     : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
+                                          static_cast<double>(uu[j]) * m2);
+    }
   }
 }
 
@@ -72,32 +138,25 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
   const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
 
   // ---- gather the N-sample window (zero outside the block) ---------------------------------
-  for (int n = tid * 4; n < N; n += T * 4) {
+  constexpr int SG = kGatherLane;
+  for (int n = tid * SG; n < N; n += T * SG) {
     const int64_t g = in0 + n;
-    float v[4];
-    if (g >= b0 && g + 4 <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
-      const int4 k4 = *reinterpret_cast<const int4*>(lpix + g);
-      const float4 q4 = *reinterpret_cast<const float4*>(wq + g);
-      const float4 u4 = *reinterpret_cast<const float4*>(wu + g);
-      float4 d4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if constexpr (kFromData) d4 = *reinterpret_cast<const float4*>(d + g);
-      v[0] = gather_one<kFromData>(k4.x, q4.x, u4.x, x, d4.x);
-      v[1] = gather_one<kFromData>(k4.y, q4.y, u4.y, x, d4.y);
-      v[2] = gather_one<kFromData>(k4.z, q4.z, u4.z, x, d4.z);
-      v[3] = gather_one<kFromData>(k4.w, q4.w, u4.w, x, d4.w);
+    float v[SG];
+    if (g >= b0 && g + SG <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
+      gather_lane<SG, kFromData>(lpix, wq, wu, x, d, g, v);
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < SG; ++j) {
         const int64_t gj = g + j;
         v[j] = 0.0f;
         if (gj >= b0 && gj < b1)
           v[j] = gather_one<kFromData>(lpix[gj], wq[gj], wu[gj], x, kFromData ? d[gj] : 0.0f);
       }
     }
-    // samples n..n+3 are complex points n/2, n/2+1 (n/2 even: adjacent after padding)
+    // samples n..n+SG-1 are complex points n/2.. (n/2 even: contiguous pairs after padding)
     float2* dst = buf + pad(n >> 1);
-    dst[0] = make_float2(v[0], v[1]);
-    dst[1] = make_float2(v[2], v[3]);
+#pragma unroll
+    for (int j = 0; j < SG / 2; ++j) dst[j] = make_float2(v[2 * j], v[2 * j + 1]);
   }
   __syncthreads();
 
@@ -107,29 +166,35 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
   fft_forward<LOG, T>(buf, tw0, tw1);
 
   // ---- scatter the segment's outputs ----------------------------------------------------------
+  constexpr int SS = kScatterLane;
   const AtomicFlush flush{y};
-  for (int base = 0; base < c.out_len; base += T * 4) {  // same trip count for every lane
-    const int i0 = base + tid * 4;
+  for (int base = 0; base < c.out_len; base += T * SS) {  // same trip count for every lane
+    const int i0 = base + tid * SS;
     const int64_t o = c.out0 + i0;
-    int key[4] = {-1, -1, -1, -1};
-    double v[4][3];
-    if (i0 + 4 <= c.out_len && (o & 3) == 0) {
-      const int4 k4 = *reinterpret_cast<const int4*>(lpix + o);
-      const float4 q4 = *reinterpret_cast<const float4*>(wq + o);
-      const float4 w4 = *reinterpret_cast<const float4*>(wu + o);
-      key[0] = k4.x; key[1] = k4.y; key[2] = k4.z; key[3] = k4.w;
-      const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
-      const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+    int key[SS];
+    double v[SS][3];
+    if (i0 + SS <= c.out_len && (o & 3) == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double tv = real_out(buf, lam + i0 + j);
-        v[j][0] = tv;
-        v[j][1] = static_cast<double>(qq[j]) * tv;
-        v[j][2] = static_cast<double>(ww[j]) * tv;
+      for (int cc = 0; cc < SS / 4; ++cc) {
+        const int4 k4 = *reinterpret_cast<const int4*>(lpix + o + 4 * cc);
+        const float4 q4 = *reinterpret_cast<const float4*>(wq + o + 4 * cc);
+        const float4 w4 = *reinterpret_cast<const float4*>(wu + o + 4 * cc);
+        const int kq[4] = {k4.x, k4.y, k4.z, k4.w};
+        const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
+        const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double tv = real_out(buf, lam + i0 + 4 * cc + j);
+          key[4 * cc + j] = kq[j];
+          v[4 * cc + j][0] = tv;
+          v[4 * cc + j][1] = static_cast<double>(qq[j]) * tv;
+          v[4 * cc + j][2] = static_cast<double>(ww[j]) * tv;
+        }
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < SS; ++j) {
+        key[j] = -1;
         v[j][0] = v[j][1] = v[j][2] = 0.0;
         if (i0 + j < c.out_len) {
           const int64_t oj = o + j;
@@ -141,7 +206,7 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
         }
       }
     }
-    wave_merge_runs<3>(key, v, flush);
+    wave_merge_runs_n<SS, 3>(key, v, flush);
   }
 }
 
