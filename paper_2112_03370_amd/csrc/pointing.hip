@@ -2,12 +2,14 @@
 // operations), plus the data mask used for the right-hand side.
 //
 // Layout: per-sample arrays are separate coalesced streams (local pixel int32, cos/sin FP32);
-// each thread owns 4 consecutive samples so every stream is read with one 16-byte load.
-// Pixel-domain vectors are FP64 [n_kept][3] and stay cache-resident while the time streams go
-// by.  P^T accumulates in FP64: samples of one pixel arrive in runs (the scan dwells on a pixel
-// for several samples), so each thread first sums its own run pieces, then a wavefront
-// segmented scan merges runs that continue across lanes, and only the lane that closes a run
-// issues the three FP64 atomic adds.
+// each thread owns 8 consecutive samples, read with two 16-byte loads per stream.  Pixel-domain
+// vectors are FP64 [n_kept][3] and stay cache-resident while the time streams go by; the
+// un-pointing loads a pixel's three values only when the pixel changes from the thread's
+// previous sample (scan runs make that rare), since these kernels are bound by the count of
+// vector memory instructions rather than by bytes.  P^T accumulates in FP64: samples of one
+// pixel arrive in runs (the scan dwells on a pixel for several samples), so each thread first
+// sums its own run pieces, then a wavefront segmented scan merges runs that continue across
+// lanes, and only the lane that closes a run issues the three FP64 atomic adds.
 #include "mm_internal.h"
 #include "wave_runs.h"
 
@@ -16,11 +18,13 @@ namespace mm {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPerThread = 4;
+constexpr int kPerThread = 4;              // diagonal kernel
 constexpr int kPerBlock = kThreads * kPerThread;
+constexpr int kLane = 8;                   // un-pointing and pointing
+constexpr int kLaneBlock = kThreads * kLane;
 
-inline int grid_for(int64_t n) {
-  int64_t g = (n + kPerBlock - 1) / kPerBlock;
+inline int grid_for(int64_t n, int per_block = kPerBlock) {
+  int64_t g = (n + per_block - 1) / per_block;
   if (g < 1) g = 1;
   if (g > 65536) g = 65536;
   return static_cast<int>(g);
@@ -33,26 +37,39 @@ __global__ __launch_bounds__(kThreads) void k_unpoint(const int32_t* __restrict_
                                                       float* __restrict__ t, int64_t n,
                                                       const int32_t* __restrict__ done) {
   if (done != nullptr && *done) return;
-  for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kPerThread;
-       i0 < n; i0 += static_cast<int64_t>(gridDim.x) * kPerBlock) {
-    if (i0 + kPerThread <= n) {
-      const int4 k4 = *reinterpret_cast<const int4*>(lpix + i0);
-      const float4 q4 = *reinterpret_cast<const float4*>(wq + i0);
-      const float4 u4 = *reinterpret_cast<const float4*>(wu + i0);
-      const int key[4] = {k4.x, k4.y, k4.z, k4.w};
-      const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
-      const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
-      float out[4];
+  for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kLane;
+       i0 < n; i0 += static_cast<int64_t>(gridDim.x) * kLaneBlock) {
+    if (i0 + kLane <= n) {
+      int key[kLane];
+      float qq[kLane], uu[kLane], out[kLane];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double v = 0.0;
-        if (key[j] >= 0) {
-          const double* m = x + 3 * static_cast<int64_t>(key[j]);
-          v = m[0] + static_cast<double>(qq[j]) * m[1] + static_cast<double>(uu[j]) * m[2];
-        }
-        out[j] = static_cast<float>(v);
+      for (int c = 0; c < kLane / 4; ++c) {
+        const int4 k4 = *reinterpret_cast<const int4*>(lpix + i0 + 4 * c);
+        const float4 q4 = *reinterpret_cast<const float4*>(wq + i0 + 4 * c);
+        const float4 u4 = *reinterpret_cast<const float4*>(wu + i0 + 4 * c);
+        key[4 * c] = k4.x; key[4 * c + 1] = k4.y; key[4 * c + 2] = k4.z; key[4 * c + 3] = k4.w;
+        qq[4 * c] = q4.x; qq[4 * c + 1] = q4.y; qq[4 * c + 2] = q4.z; qq[4 * c + 3] = q4.w;
+        uu[4 * c] = u4.x; uu[4 * c + 1] = u4.y; uu[4 * c + 2] = u4.z; uu[4 * c + 3] = u4.w;
       }
-      *reinterpret_cast<float4*>(t + i0) = make_float4(out[0], out[1], out[2], out[3]);
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+      int cur = -1;
+#pragma unroll
+      for (int j = 0; j < kLane; ++j) {
+        if (key[j] >= 0 && key[j] != cur) {
+          const double* m = x + 3 * static_cast<int64_t>(key[j]);
+          m0 = m[0];
+          m1 = m[1];
+          m2 = m[2];
+          cur = key[j];
+        }
+        out[j] = key[j] < 0 ? 0.0f
+                            : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
+                                                 static_cast<double>(uu[j]) * m2);
+      }
+#pragma unroll
+      for (int c = 0; c < kLane / 4; ++c)
+        *reinterpret_cast<float4*>(t + i0 + 4 * c) =
+            make_float4(out[4 * c], out[4 * c + 1], out[4 * c + 2], out[4 * c + 3]);
     } else {
       for (int64_t i = i0; i < n; ++i) {
         const int k = lpix[i];
@@ -115,31 +132,36 @@ __global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ 
   if (done != nullptr && *done) return;
   const PointFlush flush{y};
   // Every lane of the block runs the same number of iterations (wavefront-collective scan).
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kPerBlock; base < n;
-       base += static_cast<int64_t>(gridDim.x) * kPerBlock) {
-    const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kPerThread;
-    int key[4] = {-1, -1, -1, -1};
-    double v[4][3];
-    if (kVec && i0 + kPerThread <= n) {
-      const int4 k4 = *reinterpret_cast<const int4*>(lpix + i0);
-      const float4 q4 = *reinterpret_cast<const float4*>(wq + i0);
-      const float4 w4 = *reinterpret_cast<const float4*>(wu + i0);
-      const float4 t4 = *reinterpret_cast<const float4*>(u + i0);
-      key[0] = k4.x; key[1] = k4.y; key[2] = k4.z; key[3] = k4.w;
-      const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
-      const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
-      const float tt[4] = {t4.x, t4.y, t4.z, t4.w};
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kLaneBlock; base < n;
+       base += static_cast<int64_t>(gridDim.x) * kLaneBlock) {
+    const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kLane;
+    int key[kLane];
+    double v[kLane][3];
+    if (kVec && i0 + kLane <= n) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double tv = tt[j];
-        v[j][0] = tv;
-        v[j][1] = static_cast<double>(qq[j]) * tv;
-        v[j][2] = static_cast<double>(ww[j]) * tv;
+      for (int c = 0; c < kLane / 4; ++c) {
+        const int4 k4 = *reinterpret_cast<const int4*>(lpix + i0 + 4 * c);
+        const float4 q4 = *reinterpret_cast<const float4*>(wq + i0 + 4 * c);
+        const float4 w4 = *reinterpret_cast<const float4*>(wu + i0 + 4 * c);
+        const float4 t4 = *reinterpret_cast<const float4*>(u + i0 + 4 * c);
+        const int kq[4] = {k4.x, k4.y, k4.z, k4.w};
+        const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
+        const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+        const float tt[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double tv = tt[j];
+          key[4 * c + j] = kq[j];
+          v[4 * c + j][0] = tv;
+          v[4 * c + j][1] = static_cast<double>(qq[j]) * tv;
+          v[4 * c + j][2] = static_cast<double>(ww[j]) * tv;
+        }
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kLane; ++j) {
         const int64_t i = i0 + j;
+        key[j] = -1;
         v[j][0] = v[j][1] = v[j][2] = 0.0;
         if (i < n) {
           key[j] = lpix[i];
@@ -150,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ 
         }
       }
     }
-    wave_merge_runs<3>(key, v, flush);
+    wave_merge_runs_n<kLane, 3>(key, v, flush);
   }
 }
 
@@ -240,7 +262,7 @@ mm_status launch_unpoint(Plan* P, const double* x, float* t, const int32_t* done
   if (n == 0) return MM_OK;
   TimedLaunch tl(P, K_UNPOINT, s);
   if (aligned16(t)) {
-    hipLaunchKernelGGL(k_unpoint, dim3(grid_for(n)), dim3(kThreads), 0, s, P->lpix, P->wq, P->wu,
+    hipLaunchKernelGGL(k_unpoint, dim3(grid_for(n, kLaneBlock)), dim3(kThreads), 0, s, P->lpix, P->wq, P->wu,
                        x, t, n, done);
   } else {
     int64_t g = (n + kThreads - 1) / kThreads;
@@ -270,10 +292,10 @@ mm_status launch_point(Plan* P, const float* u, double* y, bool zero_first, cons
   if (n == 0 || P->n_kept == 0) return MM_OK;
   TimedLaunch tl(P, K_POINT, s);
   if (aligned16(u)) {
-    hipLaunchKernelGGL(k_point<true>, dim3(grid_for(n)), dim3(kThreads), 0, s, P->lpix, P->wq,
+    hipLaunchKernelGGL(k_point<true>, dim3(grid_for(n, kLaneBlock)), dim3(kThreads), 0, s, P->lpix, P->wq,
                        P->wu, u, y, n, done);
   } else {
-    hipLaunchKernelGGL(k_point<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, P->lpix, P->wq,
+    hipLaunchKernelGGL(k_point<false>, dim3(grid_for(n, kLaneBlock)), dim3(kThreads), 0, s, P->lpix, P->wq,
                        P->wu, u, y, n, done);
   }
   MM_HIP_TRY(hipGetLastError());
