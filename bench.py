@@ -489,19 +489,26 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
 
+    phases = []
+
     def step(timing=False):
         with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
             plan = mm.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
                            prob.blk_band, prob.bands, det_offset=prob.det_offset,
                            flags=mm.FLAG_UNFUSED if args.unfused else 0, stream=stream)
+            t1 = time.perf_counter()
             if timing:
                 plan.set_timing(True)
             x, info = plan.pcg_solve(d, tol=args.tol, stream=stream)
+            t2 = time.perf_counter()
             kt = None
             if timing:
                 kt = {k: plan.kernel_time(k) for k in range(4)}
             pinfo = plan.info
             plan.close()
+            t3 = time.perf_counter()
+        phases.append((t1 - t0, t2 - t1, t3 - t2))
         return x, info, pinfo, kt
 
     for w in range(args.warmup):
@@ -553,6 +560,8 @@ def main():
     per_kernel = {names[k]: {"total_ms": round(tot[k], 2), "launches": cnt[k],
                              "avg_ms": round(tot[k] / max(1, cnt[k]), 4)} for k in range(4)}
     log(f"[bench] per-kernel (timed steps): {json.dumps(per_kernel)}")
+    ph = np.mean(np.array(phases[-args.steps:]), axis=0) * 1e3
+    log(f"[bench] step phases (ms): plan {ph[0]:.1f}, solve {ph[1]:.1f}, release {ph[2]:.1f}")
 
     if args.copy_probe_gib > 0:
         nbytes = int(args.copy_probe_gib * (1 << 30))

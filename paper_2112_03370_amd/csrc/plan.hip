@@ -244,6 +244,10 @@ __global__ __launch_bounds__(kThreads) void k_plan_remap(const int32_t* __restri
 }
 
 // ---- band symbols f(w) = c_0 + 2 sum_k c_k cos(k w) on an M-point grid (Clenshaw, FP64) -----
+// Each thread runs kSymPts independent recurrences (grid points k, k + S, k + 2S, ... with S the
+// number of threads of the band) that share every coefficient load: one chain alone would wait
+// on its own FMA latency at every step.
+constexpr int kSymPts = 4;
 
 __global__ __launch_bounds__(kThreads) void k_band_symbol(
     const float* __restrict__ coef, const int64_t* __restrict__ off,
@@ -253,27 +257,41 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
   const int band = blockIdx.y;
   const int nc = ncoef[band];
   const float* cs = coef + off[band];  // every lane reads the same coefficient: broadcast loads
-  const int k = blockIdx.x * kThreads + threadIdx.x;
-  double f = INFINITY;
-  if (k <= M / 2) {
-    const double x = cospi(2.0 * static_cast<double>(k) / static_cast<double>(M));
-    double b1 = 0.0, b2 = 0.0;
-    for (int j = nc - 1; j >= 1; --j) {
-      const double b0 = 2.0 * static_cast<double>(cs[j]) + 2.0 * x * b1 - b2;
-      b2 = b1;
-      b1 = b0;
+  const int stride = gridDim.x * kThreads;
+  int k[kSymPts];
+  double x[kSymPts], b1[kSymPts], b2[kSymPts];
+#pragma unroll
+  for (int p = 0; p < kSymPts; ++p) {
+    k[p] = blockIdx.x * kThreads + threadIdx.x + p * stride;
+    x[p] = cospi(2.0 * static_cast<double>(k[p]) / static_cast<double>(M));
+    b1[p] = 0.0;
+    b2[p] = 0.0;
+  }
+  for (int j = nc - 1; j >= 1; --j) {
+    const double c2 = 2.0 * static_cast<double>(cs[j]);
+#pragma unroll
+    for (int p = 0; p < kSymPts; ++p) {
+      const double b0 = c2 + 2.0 * x[p] * b1[p] - b2[p];
+      b2[p] = b1[p];
+      b1[p] = b0;
     }
-    f = static_cast<double>(cs[0]) + x * b1 - b2;
+  }
+  double m = INFINITY;
+  const double c0 = static_cast<double>(cs[0]);
+#pragma unroll
+  for (int p = 0; p < kSymPts; ++p) {
+    if (k[p] > M / 2) continue;
+    const double f = c0 + x[p] * b1[p] - b2[p];
+    m = fmin(m, f);
     if (spec != nullptr) {
       const int step = M / fft_n;
-      if (k % step == 0) {
-        const int kk = k / step;  // 0 .. fft_n / 2
+      if (k[p] % step == 0) {
+        const int kk = k[p] / step;  // 0 .. fft_n / 2
         spec[static_cast<int64_t>(band) * (fft_n / 2 + 1) + kk] =
             static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
       }
     }
   }
-  double m = f;
   for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_down(m, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -664,7 +682,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     while (M < 8 * lambda_max) M *= 2;
     if (fft_n > M) M = fft_n;
     if (algo == MM_TOEPLITZ_FFT) MM_TRY(dalloc(P, &P->spec, static_cast<size_t>(g->n_bands) * (fft_n / 2 + 1)));
-    const int gx = (M / 2 + 1 + kThreads - 1) / kThreads;
+    const int gx = (M / 2 + 1 + kThreads * kSymPts - 1) / (kThreads * kSymPts);
     Scratch<double> mins;
     MM_TRY(mins.alloc(static_cast<size_t>(gx) * g->n_bands));
     hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
