@@ -127,6 +127,8 @@ typedef struct {
                              0 or 1 each column alone (Alg. 1); 2..32 that many at a time;
                              < 0 tune among 8, 16, 32 on the first column groups; the
                              plan keeps the choice, and later tuned solves start with it */
+  int32_t precond;        /* 0 block-Jacobi M_BD; 1 two-level M_2lvl (Eq. 2lvlDef), which needs
+                             mm_deflation_build on the plan and block 0/1 */
 } mm_solve_opts;
 
 typedef struct {
@@ -200,6 +202,36 @@ mm_status mm_precond_bj(const mm_plan_t* plan, const double* r, double* z, int32
 mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d,
                        double* x, const mm_solve_opts* opts, mm_solve_info* info,
                        void* stream);
+
+/* ---- Two-level a posteriori preconditioner (Eq. 2lvlDef, A-DEF1; Alg. 3) ------------------
+ * mm_deflation_build runs m steps of Lanczos (Alg. 3) on A = P^T N^-1 P from r0 = b =
+ * P^T N^-1 d (d: one right-hand side, DEVICE float [n_samples]), keeps the Lanczos vectors
+ * V_m and the products A V_m on the device (the plan owns them: 2 m + 1 pixel-domain FP64
+ * vectors), forms the coarse matrix E = V_m^T A V_m and its FP64 pseudo-inverse
+ * (eigen-directions below 1e-12 of the largest dropped; the paper's Ritz rotation of V_m is
+ * not needed since M_2lvl depends on span(V_m) only).  Later solves with opts.precond = 1
+ * apply M_2lvl = M_BD (I - A Q) + Q, Q = Z E^+ Z^T, as in Eq. 2lvlDef0.  Synchronous; m in
+ * [1, 128]; the process stops early when beta_(k+1) falls below machine precision.  Errors:
+ * MM_ERR_INVALID (m out of range, b = 0), MM_ERR_OOM, MM_ERR_HIP.  A new build replaces the
+ * previous one; mm_deflation_clear releases it. */
+typedef struct {
+  int32_t m;              /* Lanczos steps taken = columns of the deflation space */
+  int32_t rank;           /* directions kept by the pseudo-inverse of E */
+  double e_min;           /* smallest kept eigenvalue of E */
+  double e_max;           /* largest eigenvalue of E */
+  double build_ms;
+  int64_t device_bytes;
+} mm_deflation_info_t;
+
+mm_status mm_deflation_build(mm_plan_t* plan, const float* d, int32_t m, void* stream);
+mm_status mm_deflation_info(const mm_plan_t* plan, mm_deflation_info_t* out);
+mm_status mm_deflation_clear(mm_plan_t* plan);
+/* Copies the deflation vectors V_m to z (DEVICE double [m][n_kept][3], m from the info). */
+mm_status mm_deflation_vectors(const mm_plan_t* plan, double* z, void* stream);
+/* z = M_2lvl r (Eq. 2lvlDef0), r and z DEVICE double [k][n_kept][3], must not alias.  Needs a
+ * built deflation space (MM_ERR_INVALID otherwise).  Asynchronous. */
+mm_status mm_precond_2lvl(const mm_plan_t* plan, const double* r, double* z, int32_t k,
+                          void* stream);
 
 /* Per-kernel timing (HIP events recorded on the launch stream around every launch of the
  * plan's kernels while enabled; graphs are not used then).  kind: 0 un-pointing, 1 Toeplitz

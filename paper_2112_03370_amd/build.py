@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmm.so")
-SOURCES = ["api.hip", "plan.hip", "pointing.hip", "toeplitz.hip", "toeplitz_long.hip", "apply_fused.hip", "cg.hip", "block.hip", "server.hip"]
+SOURCES = ["api.hip", "plan.hip", "pointing.hip", "toeplitz.hip", "toeplitz_long.hip", "apply_fused.hip", "cg.hip", "block.hip", "server.hip",
+           "deflation.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

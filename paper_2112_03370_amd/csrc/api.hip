@@ -244,8 +244,12 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
+    if (opts && opts->precond != 0 && opts->precond != 1) return fail(MM_ERR_INVALID, "precond must be 0 or 1");
+    if (opts && opts->precond == 1 && P->defl.m == 0)
+      return fail(MM_ERR_INVALID, "precond = 1 needs mm_deflation_build first");
     if (opts && opts->block != 0 && opts->block != 1 && k > 0) {
       if (opts->use_x0) return fail(MM_ERR_INVALID, "use_x0 is not supported with block != 0/1");
+      if (opts->precond == 1) return fail(MM_ERR_UNSUPPORTED, "stacked solves use block-Jacobi");
       return block_solve(P, P->work, d, k, ld_d, x, opts, info, s);
     }
     mm_status worst = MM_OK;
@@ -262,6 +266,71 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
     }
     if (worst != MM_OK) set_error(msg);
     return worst;
+  });
+}
+
+mm_status mm_deflation_build(mm_plan_t* plan, const float* d, int32_t m, void* stream) {
+  MM_TRY(check_plan(plan));
+  Plan* P = as_plan(plan);
+  MM_TRY(check_device(P));
+  if (m < 1 || m > kMaxDeflation) return fail(MM_ERR_INVALID, "m out of [1, 128]");
+  if (P->n_samples > 0 && !d) return fail(MM_ERR_INVALID, "NULL data");
+  if (P->n_kept == 0) return fail(MM_ERR_INVALID, "plan has no kept pixels");
+  std::lock_guard<std::mutex> lock(P->mu);
+  return guarded([&]() -> mm_status { return deflation_build(P, d, m, as_stream(stream)); });
+}
+
+mm_status mm_deflation_info(const mm_plan_t* plan, mm_deflation_info_t* out) {
+  MM_TRY(check_plan(plan));
+  if (!out) return fail(MM_ERR_INVALID, "out is NULL");
+  const Plan* P = as_plan(plan);
+  out->m = P->defl.m;
+  out->rank = P->defl.rank;
+  out->e_min = P->defl.e_min;
+  out->e_max = P->defl.e_max;
+  out->build_ms = P->defl.build_ms;
+  out->device_bytes = P->defl.bytes;
+  return MM_OK;
+}
+
+mm_status mm_deflation_clear(mm_plan_t* plan) {
+  MM_TRY(check_plan(plan));
+  Plan* P = as_plan(plan);
+  std::lock_guard<std::mutex> lock(P->mu);
+  deflation_free(&P->defl);
+  return MM_OK;
+}
+
+mm_status mm_deflation_vectors(const mm_plan_t* plan, double* z, void* stream) {
+  MM_TRY(check_plan(plan));
+  const Plan* P = as_plan(plan);
+  MM_TRY(check_device(P));
+  if (P->defl.m == 0) return fail(MM_ERR_INVALID, "no deflation space built");
+  if (!z) return fail(MM_ERR_INVALID, "NULL output");
+  const size_t bytes = sizeof(double) * static_cast<size_t>(P->defl.m) * 3 * P->n_kept;
+  return guarded([&]() -> mm_status {
+    MM_HIP_TRY(hipMemcpyAsync(z, P->defl.Z, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+    return MM_OK;
+  });
+}
+
+mm_status mm_precond_2lvl(const mm_plan_t* plan, const double* r, double* z, int32_t k,
+                          void* stream) {
+  MM_TRY(check_plan(plan));
+  Plan* P = as_plan(plan);
+  MM_TRY(check_device(P));
+  if (k < 0) return fail(MM_ERR_INVALID, "k < 0");
+  if (P->defl.m == 0) return fail(MM_ERR_INVALID, "no deflation space built");
+  if (k > 0 && (!r || !z)) return fail(MM_ERR_INVALID, "NULL vector");
+  if (k > 0 && r == z) return fail(MM_ERR_INVALID, "r and z must not alias");
+  hipStream_t s = as_stream(stream);
+  std::lock_guard<std::mutex> lock(P->mu);
+  return guarded([&]() -> mm_status {
+    const int64_t nu = 3 * P->n_kept;
+    for (int32_t j = 0; j < k; ++j)
+      MM_TRY(deflation_apply(P, r + j * nu, z + j * nu, nullptr, P->work.partial, P->work.nrb,
+                             nullptr, s));
+    return MM_OK;
   });
 }
 

@@ -215,55 +215,6 @@ __global__ void k_zero_cols(double* __restrict__ x, const int32_t* __restrict__ 
 
 // ---- host-side t x t algebra (FP64) ---------------------------------------------------------
 
-// Pseudo-inverse of a symmetric positive semi-definite n x n matrix (row-major) by cyclic
-// Jacobi eigen-decomposition; eigenvalues below rtol * largest are dropped.
-void sym_pinv(const std::vector<double>& G, int n, double rtol, std::vector<double>& out) {
-  std::vector<double> a(G), v(static_cast<size_t>(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += a[i * n + j] * a[i * n + j];
-        if (i != j) off += a[i * n + j] * a[i * n + j];
-      }
-    if (off <= 1e-30 * tot || tot == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = a[p * n + q];
-        if (apq == 0.0) continue;
-        const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double akp = a[k * n + p], akq = a[k * n + q];
-          a[k * n + p] = c * akp - s * akq;
-          a[k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double apk = a[p * n + k], aqk = a[q * n + k];
-          a[p * n + k] = c * apk - s * aqk;
-          a[q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {  // eigenvectors
-          const double vkp = v[k * n + p], vkq = v[k * n + q];
-          v[k * n + p] = c * vkp - s * vkq;
-          v[k * n + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  double wmax = 0.0;
-  for (int i = 0; i < n; ++i) wmax = std::max(wmax, a[i * n + i]);
-  out.assign(static_cast<size_t>(n) * n, 0.0);
-  for (int e = 0; e < n; ++e) {
-    const double w = a[e * n + e];
-    if (!(w > rtol * wmax) || w <= 0.0) continue;
-    const double inv = 1.0 / w;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) out[i * n + j] += v[i * n + e] * inv * v[j * n + e];
-  }
-}
-
 // C (n x m) = A (n x n) B (n x m), row-major
 void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, int m,
             std::vector<double>& C) {
@@ -480,6 +431,62 @@ mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x
 }
 
 }  // namespace
+
+// Pseudo-inverse of a symmetric positive semi-definite n x n matrix (row-major) by cyclic
+// Jacobi eigen-decomposition; eigenvalues below rtol * largest are dropped.
+void sym_pinv(const std::vector<double>& G, int n, double rtol, std::vector<double>& out,
+              SymPinvInfo* info) {
+  std::vector<double> a(G), v(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a[i * n + j] * a[i * n + j];
+        if (i != j) off += a[i * n + j] * a[i * n + j];
+      }
+    if (off <= 1e-30 * tot || tot == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // eigenvectors
+          const double vkp = v[k * n + p], vkq = v[k * n + q];
+          v[k * n + p] = c * vkp - s * vkq;
+          v[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double wmax = 0.0;
+  for (int i = 0; i < n; ++i) wmax = std::max(wmax, a[i * n + i]);
+  out.assign(static_cast<size_t>(n) * n, 0.0);
+  if (info) *info = SymPinvInfo{0, INFINITY, wmax};
+  for (int e = 0; e < n; ++e) {
+    const double w = a[e * n + e];
+    if (!(w > rtol * wmax) || w <= 0.0) continue;
+    if (info) {
+      info->rank += 1;
+      info->wmin = std::min(info->wmin, w);
+    }
+    const double inv = 1.0 / w;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) out[i * n + j] += v[i * n + e] * inv * v[j * n + e];
+  }
+}
+
 
 mm_status block_solve(Plan* P, Work& Wk, const float* d, int32_t k, int64_t ld_d, double* x,
                       const mm_solve_opts* o, mm_solve_info* info, hipStream_t s) {

@@ -242,8 +242,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce_to(double* out, const doubl
   if (threadIdx.x == 0) *out = s;
 }
 
-// One PCG iteration (all launches gated by state->done).
-mm_status iteration(Plan* P, Work& W, double* x, hipStream_t s) {
+// One PCG iteration (all launches gated by state->done).  With the two-level preconditioner,
+// z = M_2lvl r replaces the block-Jacobi z of k_update (and its <r, z> partials) before beta.
+mm_status iteration(Plan* P, Work& W, double* x, bool two_level, hipStream_t s) {
   const int32_t* done = &W.state->done;
   const int nrb = W.nrb;
   const int64_t nk = P->n_kept;
@@ -262,6 +263,7 @@ mm_status iteration(Plan* P, Work& W, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
   hipLaunchKernelGGL(k_update, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z, W.p,
                      W.q, nk, W.partial, nrb, W.state);
+  if (two_level) MM_TRY(deflation_apply(P, W.r, W.z, nullptr, W.partial, nrb, done, s));
   hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
   hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, W.z, W.p, 3 * nk, W.state);
   MM_HIP_TRY(hipGetLastError());
@@ -370,6 +372,11 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
   if (opts.use_x0) MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
   hipLaunchKernelGGL(k_init, dim3(nrb), dim3(kThreads), 0, s, P->minv, W.b, W.q, W.r, W.z,
                      W.p, W.q, x, opts.use_x0 ? 1 : 0, nk, W.partial, nrb);
+  const bool two_level = opts.precond == 1;
+  if (two_level) {
+    if (P->defl.m == 0) return fail(MM_ERR_INVALID, "precond = 1 needs a deflation space");
+    MM_TRY(deflation_apply(P, W.r, W.z, W.p, W.partial, nrb, nullptr, s));  // z0 = p0 = M r0
+  }
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb, tol,
                      max_iter);
   MM_HIP_TRY(hipGetLastError());
@@ -408,7 +415,7 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
         std::shared_lock<std::shared_mutex> gate(alloc_gate());
         MM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         mm_status st = MM_OK;
-        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, s);
+        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, two_level, s);
         hipError_t ce = hipStreamEndCapture(s, &graph);
         gate.unlock();
         if (st != MM_OK) {
@@ -430,7 +437,7 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
     } else {
       for (int i = 0; i < chunk; ++i) {
         if (P->timing.enabled) P->timing.tag = queued + i + 1;
-        MM_TRY(iteration(P, W, x, s));
+        MM_TRY(iteration(P, W, x, two_level, s));
       }
       if (P->timing.enabled) P->timing.tag = 0;
     }

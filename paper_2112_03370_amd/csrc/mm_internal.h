@@ -108,6 +108,24 @@ struct Work {
   int64_t bytes = 0;
 };
 
+// Two-level preconditioner state (deflation.hip): Lanczos basis V_m (Z), the stored products
+// A V_m (Zp), the pseudo-inverse of E = Z^T Zp, and scratch for its application.
+constexpr int32_t kMaxDeflation = 128;
+
+struct Deflation {
+  int32_t m = 0;               // columns of Z (Lanczos steps taken)
+  int32_t rank = 0;            // rank kept by the pseudo-inverse of E
+  double e_min = 0.0;          // smallest kept eigenvalue of E
+  double e_max = 0.0;          // largest eigenvalue of E
+  double build_ms = 0.0;
+  int64_t bytes = 0;
+  double* Z = nullptr;         // [m + 1][3 n_kept]
+  double* Zp = nullptr;        // [m][3 n_kept]
+  double* einv = nullptr;      // [m][m]
+  double* partial = nullptr;   // dot partials
+  double* c = nullptr;         // [kMaxDeflation] coefficients + scalars
+};
+
 struct Plan;
 int64_t work_bytes(const Plan* P);
 mm_status work_alloc(const Plan* P, Work* W);
@@ -164,6 +182,7 @@ struct Plan {
   std::vector<int64_t> h_id_seg;
 
   Work work;                    // workspace of the plain calls (serialized by mu)
+  Deflation defl;               // two-level preconditioner (built on request, under mu)
   hipStream_t aux = nullptr;    // plan-owned stream for graph replay when the caller's is null
 
   Timing timing;
@@ -236,6 +255,24 @@ mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* 
 // Stacked right-hand sides by the enlarged-CG recurrences (block.hip).
 mm_status block_solve(Plan* P, Work& W, const float* d, int32_t k, int64_t ld_d, double* x,
                       const mm_solve_opts* o, mm_solve_info* info, hipStream_t s);
+
+// Pseudo-inverse of a symmetric positive semi-definite n x n matrix (row-major, host FP64) by
+// cyclic Jacobi; eigenvalues <= rtol * largest are dropped (block.hip).
+struct SymPinvInfo {
+  int rank;
+  double wmin;   // smallest kept eigenvalue
+  double wmax;   // largest eigenvalue
+};
+void sym_pinv(const std::vector<double>& G, int n, double rtol, std::vector<double>& out,
+              SymPinvInfo* info = nullptr);
+
+// Two-level preconditioner (deflation.hip): build from d (Lanczos on A from b = P^T N^-1 d),
+// release, and apply z = M_2lvl r (p = z too when p != null) writing the <r, z> partials to
+// partial[nrb + block] as the CG scalar kernels expect (launch grid nrb).
+mm_status deflation_build(Plan* P, const float* d, int32_t m, hipStream_t s);
+void deflation_free(Deflation* D);
+mm_status deflation_apply(Plan* P, const double* r, double* z, double* p, double* partial, int nrb,
+                          const int32_t* done, hipStream_t s);
 
 // Plan construction (plan.hip).
 mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out);

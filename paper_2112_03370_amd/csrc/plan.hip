@@ -482,6 +482,7 @@ void destroy_plan(Plan* P) {
                   P->id_seg};
   for (void* p : ptrs) dev_free(p);
   work_free(&P->work);
+  deflation_free(&P->defl);
   if (P->aux) (void)hipStreamDestroy(P->aux);
   for (int k = 0; k < K_NKINDS; ++k)
     for (const TimedPair& t : P->timing.pending[k]) {

@@ -449,6 +449,8 @@ mm_status mm_submit(mm_server_t* server, uint64_t key, const float* d, int32_t k
   if (opts && opts->tol < 0) return fail(MM_ERR_INVALID, "tol < 0");
   if (opts && opts->use_x0 && opts->block != 0 && opts->block != 1)
     return fail(MM_ERR_INVALID, "use_x0 is not supported with block != 0/1");
+  if (opts && opts->precond != 0)
+    return fail(MM_ERR_UNSUPPORTED, "served solves use the block-Jacobi preconditioner");
   try {
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return fail(MM_ERR_INVALID, "server is stopping");

@@ -58,12 +58,21 @@ class PlanInfo(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", _c_dbl), ("max_iter", _c_i32), ("use_x0", _c_i32),
-                ("check_every", _c_i32), ("use_graph", _c_i32), ("block", _c_i32)]
+                ("check_every", _c_i32), ("use_graph", _c_i32), ("block", _c_i32),
+                ("precond", _c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _c_i32), ("converged", _c_i32), ("relres", _c_dbl),
                 ("true_relres", _c_dbl), ("bnorm", _c_dbl), ("ms", _c_dbl), ("block", _c_i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DeflationInfo(ctypes.Structure):
+    _fields_ = [("m", _c_i32), ("rank", _c_i32), ("e_min", _c_dbl), ("e_max", _c_dbl),
+                ("build_ms", _c_dbl), ("device_bytes", _c_i64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -118,6 +127,11 @@ def load(path: Optional[str] = None):
         "mm_pcg_solve": [_vp, _vp, _c_i32, _c_i64, _vp, P(SolveOpts), P(SolveInfo), _vp],
         "mm_set_timing": [_vp, _c_i32],
         "mm_kernel_time": [_vp, _c_i32, P(_c_dbl), P(_c_i64)],
+        "mm_deflation_build": [_vp, _vp, _c_i32, _vp],
+        "mm_deflation_info": [_vp, P(DeflationInfo)],
+        "mm_deflation_clear": [_vp],
+        "mm_deflation_vectors": [_vp, _vp, _vp],
+        "mm_precond_2lvl": [_vp, _vp, _vp, _c_i32, _vp],
         "mm_server_create": [P(ServerOpts), P(_vp)],
         "mm_server_destroy": [_vp],
         "mm_server_plan": [_vp, P(Geometry), ctypes.c_uint64, P(PlanInfo)],
@@ -298,14 +312,14 @@ class Plan:
         return z
 
     def pcg_solve(self, d, x=None, tol=1e-8, max_iter=10000, use_x0=False, check_every=0,
-                  use_graph=True, block=0, stream=None, raise_on_error=True):
+                  use_graph=True, block=0, precond=0, stream=None, raise_on_error=True):
         """block 0/1: PCG per column; >= 2: columns solved together in groups of `block` by the
         enlarged-CG recurrences; < 0: group size tuned among 8, 16, 32."""
         k = 1 if d.dim() == 1 else int(d.shape[0])
         ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
         x = x if x is not None else self._map(k)
         o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every,
-                      use_graph=int(use_graph), block=int(block))
+                      use_graph=int(use_graph), block=int(block), precond=int(precond))
         infos = (SolveInfo * max(1, k))()
         st = self._lib.mm_pcg_solve(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o), infos,
                                     _stream(stream))
@@ -315,6 +329,33 @@ class Plan:
         for r in res:
             r["status"] = STATUS.get(st, st)
         return x, (res[0] if k == 1 else res)
+
+    # ---- two-level preconditioner ------------------------------------------------------------
+    def deflation_build(self, d, m, stream=None):
+        """Lanczos (Alg. 3) from b = P^T N^-1 d, m steps; later solves may pass precond=1."""
+        check(self._lib.mm_deflation_build(self._h, _ptr(d), int(m), _stream(stream)))
+        return self.deflation_info()
+
+    def deflation_info(self) -> dict:
+        out = DeflationInfo()
+        check(self._lib.mm_deflation_info(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def deflation_clear(self):
+        check(self._lib.mm_deflation_clear(self._h))
+
+    def deflation_vectors(self, stream=None):
+        import torch
+        m = self.deflation_info()["m"]
+        z = torch.empty((m, self.n_kept, 3), dtype=torch.float64, device=self.device)
+        check(self._lib.mm_deflation_vectors(self._h, _ptr(z), _stream(stream)))
+        return z
+
+    def precond_2lvl(self, r, z=None, stream=None):
+        k = 1 if r.dim() == 2 else int(r.shape[0])
+        z = z if z is not None else self._map(k)
+        check(self._lib.mm_precond_2lvl(self._h, _ptr(r), _ptr(z), k, _stream(stream)))
+        return z
 
     # ---- timing ------------------------------------------------------------------------------
     def set_timing(self, enable: bool):

@@ -43,6 +43,9 @@ def test_status_strings_without_device():
     assert lib.mm_wait(None, 1, None, None) == -1
     assert lib.mm_server_stats(None, None) == -1
     assert lib.mm_server_plan(None, None, 1, None) == -1
+    assert lib.mm_deflation_build(None, None, 8, None) == -1
+    assert lib.mm_deflation_clear(None) == -1
+    assert lib.mm_precond_2lvl(None, None, None, 1, None) == -1
 
 
 def test_struct_layout_matches_header():
@@ -66,6 +69,8 @@ int main(void) {
   printf("mm_server_stats_t %zu\n", sizeof(mm_server_stats_t));
   P(mm_server_opts, max_bypass) P(mm_request_times, slot) P(mm_server_stats_t, queued)
   P(mm_server_stats_t, n_plans)
+  printf("mm_deflation_info_t %zu\n", sizeof(mm_deflation_info_t));
+  P(mm_deflation_info_t, build_ms) P(mm_deflation_info_t, device_bytes) P(mm_solve_opts, precond)
   return 0;
 }
 """
@@ -101,5 +106,9 @@ int main(void) {
         "mm_request_times.slot": M.RequestTimes.slot.offset,
         "mm_server_stats_t.queued": M.ServerStats.queued.offset,
         "mm_server_stats_t.n_plans": M.ServerStats.n_plans.offset,
+        "mm_deflation_info_t": ctypes.sizeof(M.DeflationInfo),
+        "mm_deflation_info_t.build_ms": M.DeflationInfo.build_ms.offset,
+        "mm_deflation_info_t.device_bytes": M.DeflationInfo.device_bytes.offset,
+        "mm_solve_opts.precond": M.SolveOpts.precond.offset,
     }
     assert {k: int(v) for k, v in got.items()} == exp
