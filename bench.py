@@ -180,6 +180,29 @@ def run_batched(args, prob, mm, torch, dev, stream):
     plain = k / plain_s
     diff = (x - xp).reshape(k, -1).norm(dim=1) / xp.reshape(k, -1).norm(dim=1).clamp_min(1e-300)
     max_diff = float(diff.max())
+
+    # two-level preconditioner: deflation space from the first right-hand side (Lanczos,
+    # counted in the time), then every column by PCG with M_2lvl
+    two = None
+    if args.defl_m > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            plan = mm.Plan(pix_d, wq_d, wu_d, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                           prob.blk_band, prob.bands, det_offset=prob.det_offset, stream=stream)
+            dinfo = plan.deflation_build(d[0], args.defl_m, stream=stream)
+            x2, infos2 = plan.pcg_solve(d, tol=args.tol, precond=1, stream=stream)
+            plan.close()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t0
+        d2 = (x2 - xp).reshape(k, -1).norm(dim=1) / xp.reshape(k, -1).norm(dim=1).clamp_min(1e-300)
+        two = {"m": args.defl_m, "rank": dinfo["rank"], "build_ms": round(dinfo["build_ms"], 1),
+               "solves_per_s": k / t2, "seconds": round(t2, 3),
+               "iterations_mean": float(np.mean([i["iterations"] for i in infos2])),
+               "iterations_first_rhs": int(infos2[0]["iterations"]),
+               "max_map_rel_diff_vs_plain": float(d2.max())}
+        log(f"[bench] two-level (m={args.defl_m}): {two['solves_per_s']:.2f} solves/s, "
+            f"build {two['build_ms']} ms, iterations mean {two['iterations_mean']:.1f}")
     log(f"[bench] batched {value:.2f} solves/s, plain {plain:.2f} solves/s "
         f"(plain iterations {min(i['iterations'] for i in pinfos)}.."
         f"{max(i['iterations'] for i in pinfos)}), max map rel diff {max_diff:.2e}")
@@ -235,6 +258,7 @@ def run_batched(args, prob, mm, torch, dev, stream):
                   "speedup": round(value / plain, 3), "max_map_rel_diff": max_diff,
                   "max_true_relres_batched": max(i["true_relres"] for i in all_infos[-1]),
                   "max_true_relres_plain": max(i["true_relres"] for i in pinfos)},
+        "two_level": two,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -456,6 +480,9 @@ def main():
     ap.add_argument("--block", type=int, default=-1,
                     help="batched workload: right-hand sides per block (-1: tuned among 8/16/32)")
     ap.add_argument("--slots", type=int, default=8, help="serving workload: solves at once")
+    ap.add_argument("--defl-m", type=int, default=64,
+                    help="batched workload: Lanczos steps of the two-level preconditioner "
+                         "(0: skip that comparison)")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving workload: Poisson rate as a fraction of sequential capacity")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,

@@ -302,10 +302,15 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
   }
 }
 
+// Stream-ordered upload (no legacy-stream operation: other threads may be capturing graphs on
+// their own streams meanwhile); synchronous, since h is released by the caller afterwards.
 template <class T>
-mm_status upload(Plan* P, T** dst, const std::vector<T>& h) {
+mm_status upload(Plan* P, T** dst, const std::vector<T>& h, hipStream_t s) {
   MM_TRY(dalloc(P, dst, h.size()));
-  if (!h.empty()) MM_HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!h.empty()) {
+    MM_HIP_TRY(hipMemcpyAsync(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+  }
   return MM_OK;
 }
 
@@ -583,11 +588,11 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   P->n_chunks = static_cast<int32_t>(chunks.size());
   P->n_id_seg = static_cast<int32_t>(idseg.size() / 2);
   P->h_id_seg = idseg;
-  MM_TRY(upload(P, &P->chunks, chunks));
-  MM_TRY(upload(P, &P->id_tiles, id_tiles));
+  MM_TRY(upload(P, &P->chunks, chunks, s));
+  MM_TRY(upload(P, &P->id_tiles, id_tiles, s));
   P->n_id_tiles = static_cast<int32_t>(id_tiles.size());
   P->fused = (g->flags & MM_FLAG_UNFUSED) == 0;
-  MM_TRY(upload(P, &P->id_seg, idseg));
+  MM_TRY(upload(P, &P->id_seg, idseg, s));
 
   // ---- bands -------------------------------------------------------------------------------
   int64_t n_coef_total = 0;
@@ -597,9 +602,9 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     std::vector<float> coef(g->band_coef, g->band_coef + n_coef_total);
     std::vector<int64_t> off(g->band_offset, g->band_offset + g->n_bands);
     std::vector<int32_t> nc(g->band_ncoef, g->band_ncoef + g->n_bands);
-    MM_TRY(upload(P, &P->band_coef, coef));
-    MM_TRY(upload(P, &P->band_off, off));
-    MM_TRY(upload(P, &P->band_ncoef, nc));
+    MM_TRY(upload(P, &P->band_coef, coef, s));
+    MM_TRY(upload(P, &P->band_off, off, s));
+    MM_TRY(upload(P, &P->band_ncoef, nc, s));
   }
 
   // ---- pointing copies + global accumulation -------------------------------------------------
@@ -715,8 +720,8 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
       const double a = -two_pi * (static_cast<double>(F) * m) / fft_n;
       t1[m] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
     }
-    MM_TRY(upload(P, &P->tw0, t0));
-    MM_TRY(upload(P, &P->tw1, t1));
+    MM_TRY(upload(P, &P->tw0, t0, s));
+    MM_TRY(upload(P, &P->tw1, t1, s));
   }
 
   // ---- workspace -----------------------------------------------------------------------------

@@ -197,3 +197,21 @@ def test_destroy_with_queued_requests(gpu_lib):
     for x in xs:
         srv.submit(9, d, x)
     srv.close()  # drops the queued requests, waits for the running one
+
+
+def test_plan_builds_while_solves_capture_graphs(gpu_lib):
+    # plan construction on the calling thread must not touch the legacy stream while worker
+    # threads capture their PCG iterations into graphs
+    import torch
+    probs = problems()
+    srv = gpu_lib.Server(n_slots=4)
+    info = srv.plan_from_problem(200, probs[3])
+    d = _dev(probs[3].d)
+    xs = [torch.empty((probs[3].d.shape[0], info["n_kept"], 3), dtype=torch.float64, device="cuda")
+          for _ in range(8)]
+    ts = [srv.submit(200, d, x) for x in xs]
+    for i, p in enumerate(probs[:3] + probs[4:]):
+        srv.plan_from_problem(300 + i, p)  # builds while the requests above run
+    for t in ts:
+        assert srv.wait(t)["status"] == "MM_OK"
+    srv.close()
