@@ -125,8 +125,9 @@ typedef struct {
   int32_t use_graph;      /* nonzero: replay iterations from a captured HIP graph */
   int32_t block;          /* right-hand sides solved together (Alg. 2 on stacked columns):
                              0 or 1 each column alone (Alg. 1); 2..32 that many at a time;
-                             < 0 tune among 8, 16, 32 on the first column groups; the
-                             plan keeps the choice, and later tuned solves start with it */
+                             < 0 tune among 1 (each alone), 8, 16, 32 on the first column
+                             groups; the choice is kept (per plan, and per problem shape for
+                             the life of the process) and later tuned solves start with it */
   int32_t precond;        /* 0 block-Jacobi M_BD; 1 two-level M_2lvl (Eq. 2lvlDef), which needs
                              mm_deflation_build on the plan and block 0/1 */
 } mm_solve_opts;

@@ -12,13 +12,19 @@
 // products, updates and the block-Jacobi apply run in the kernels below, in FP64.
 //
 // Block size: opts->block >= 2 fixes t; opts->block < 0 tunes it: the first column groups are
-// solved with t = 8, 16, 32 in turn (real work, not a rehearsal), the block size with the
-// lowest time per right-hand side then solves the remaining columns and is kept in the plan,
-// so later tuned solves on the same plan start with it.
+// solved with t = 1 (8 columns, each alone by Alg. 1), 8, 16, 32 in turn (real work, not a
+// rehearsal); the candidate with the lowest time per right-hand side then solves the remaining
+// columns and is kept in the plan and, for the life of the process, for plans of the same
+// shape, so later tuned solves start with it.  When
+// the stacked recurrences do not shorten the iteration enough to pay for their extra
+// tall-skinny work, t = 1 wins.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 
 #include "mm_internal.h"
 
@@ -488,8 +494,32 @@ void sym_pinv(const std::vector<double>& G, int n, double rtol, std::vector<doub
 }
 
 
+// Tuned block sizes by problem shape, kept for the life of the process: a plan rebuilt for the
+// same geometry starts with the size an earlier plan found.
+namespace {
+struct ShapeKey {
+  int64_t n_samples, n_kept;
+  int32_t lambda_max, fft_n, algo, fused;
+  bool operator<(const ShapeKey& o) const {
+    return std::tie(n_samples, n_kept, lambda_max, fft_n, algo, fused) <
+           std::tie(o.n_samples, o.n_kept, o.lambda_max, o.fft_n, o.algo, o.fused);
+  }
+};
+std::mutex g_tuned_mu;
+std::map<ShapeKey, int32_t> g_tuned;
+
+ShapeKey shape_of(const Plan* P) {
+  return ShapeKey{P->n_samples, P->n_kept, P->lambda_max, P->fft_n, P->algo, P->fused ? 1 : 0};
+}
+}  // namespace
+
 mm_status block_solve(Plan* P, Work& Wk, const float* d, int32_t k, int64_t ld_d, double* x,
                       const mm_solve_opts* o, mm_solve_info* info, hipStream_t s) {
+  if (o->block < 0 && P->tuned_block.load() == 0) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    auto it = g_tuned.find(shape_of(P));
+    if (it != g_tuned.end()) P->tuned_block = it->second;
+  }
   const double tol = o->tol > 0 ? o->tol : 1e-8;
   const int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
   std::vector<mm_solve_info> local(static_cast<size_t>(k));
@@ -504,7 +534,7 @@ mm_status block_solve(Plan* P, Work& Wk, const float* d, int32_t k, int64_t ld_d
   if (o->block < 0 && P->tuned_block.load() > 0) {
     best = P->tuned_block.load();  // chosen by an earlier tuned solve on this plan
   } else if (o->block < 0) {
-    candidates = {8, 16, 32};
+    candidates = {1, 8, 16, 32};  // 1: each column alone by Alg. 1
     best = candidates[0];
   } else {
     best = std::min(std::max(2, static_cast<int>(o->block)), kMaxT);
@@ -512,22 +542,39 @@ mm_status block_solve(Plan* P, Work& Wk, const float* d, int32_t k, int64_t ld_d
   int32_t next = 0;
   size_t ci = 0;
   double best_cost = INFINITY;
+  mm_solve_opts alone = *o;  // the t = 1 candidate: Alg. 1 per column
+  alone.block = 0;
+  alone.use_x0 = 0;
+  alone.precond = 0;
   while (next < k) {
     const bool tuning = ci < candidates.size();
     const int t = tuning ? candidates[ci] : best;
-    const int n = std::min<int32_t>(t, k - next);
+    const int group = t == 1 ? kMaxT / 4 : t;  // columns per group (8 for the t = 1 candidate)
+    const int n = std::min<int32_t>(group, k - next);
     std::vector<int32_t> cols(n);
     std::iota(cols.begin(), cols.end(), next);
     const auto t0 = std::chrono::steady_clock::now();
-    MM_TRY(solve_group(P, Wk, d, ld_d, x, cols, tol, max_iter, inf, t, ws, s));
+    if (t == 1) {
+      for (int32_t j : cols) {
+        const mm_status st = pcg_solve(P, Wk, d + j * ld_d, x + static_cast<int64_t>(j) * 3 * P->n_kept,
+                                       &alone, &inf[j], s);
+        if (st != MM_OK && st != MM_ERR_NO_CONV && st != MM_ERR_NOT_SPD) return st;
+      }
+    } else {
+      MM_TRY(solve_group(P, Wk, d, ld_d, x, cols, tol, max_iter, inf, t, ws, s));
+    }
     const double cost = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / n;
     if (tuning) {
-      if (n == t && cost < best_cost) {
+      if (n == group && cost < best_cost) {
         best_cost = cost;
         best = t;
       }
       ++ci;
-      if (ci == candidates.size() && best_cost < INFINITY) P->tuned_block = best;
+      if (ci == candidates.size() && best_cost < INFINITY) {
+        P->tuned_block = best;
+        std::lock_guard<std::mutex> lock(g_tuned_mu);
+        g_tuned[shape_of(P)] = best;
+      }
     }
     next += n;
   }
