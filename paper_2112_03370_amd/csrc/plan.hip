@@ -267,7 +267,24 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
     b1[p] = 0.0;
     b2[p] = 0.0;
   }
-  for (int j = nc - 1; j >= 1; --j) {
+  // eight steps per round with their eight coefficients loaded first: one wait per round
+  // instead of one per step
+  int j = nc - 1;
+  for (; j >= 8; j -= 8) {
+    double c2[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c2[q] = 2.0 * static_cast<double>(cs[j - q]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+      for (int p = 0; p < kSymPts; ++p) {
+        const double b0 = c2[q] + 2.0 * x[p] * b1[p] - b2[p];
+        b2[p] = b1[p];
+        b1[p] = b0;
+      }
+    }
+  }
+  for (; j >= 1; --j) {
     const double c2 = 2.0 * static_cast<double>(cs[j]);
 #pragma unroll
     for (int p = 0; p < kSymPts; ++p) {
