@@ -52,61 +52,85 @@ __device__ __forceinline__ float gather_one(int key, float q, float w, const dou
   }
 }
 
-// Window samples [g, g + S) of one lane, inside the block and 16-byte aligned.  Scan runs keep
-// a pixel for several consecutive samples, so the lane loads a pixel's three values only when
-// the pixel changes from its previous sample (usually once or twice per lane) instead of once
-// per sample.
+// Pointing of one lane: window samples [g, g + S), inside the block and 16-byte aligned (the
+// data instead of the weights when gathering d).
 template <int S, bool kFromData>
-__device__ __forceinline__ void gather_lane(const int32_t* __restrict__ lpix,
-                                            const float* __restrict__ wq,
-                                            const float* __restrict__ wu,
-                                            const double* __restrict__ x,
-                                            const float* __restrict__ d, int64_t g, float (&v)[S]) {
+struct LanePointing {
   int kk[S];
   float qq[S], uu[S];
+
+  __device__ __forceinline__ void load(const int32_t* __restrict__ lpix,
+                                       const float* __restrict__ wq, const float* __restrict__ wu,
+                                       const float* __restrict__ d, int64_t g) {
 #pragma unroll
-  for (int c = 0; c < S / 4; ++c) {
-    const int4 k4 = *reinterpret_cast<const int4*>(lpix + g + 4 * c);
-    kk[4 * c] = k4.x;
-    kk[4 * c + 1] = k4.y;
-    kk[4 * c + 2] = k4.z;
-    kk[4 * c + 3] = k4.w;
-    // qq holds the data when gathering d, the weights otherwise
-    const float4 q4 = *reinterpret_cast<const float4*>((kFromData ? d : wq) + g + 4 * c);
-    qq[4 * c] = q4.x;
-    qq[4 * c + 1] = q4.y;
-    qq[4 * c + 2] = q4.z;
-    qq[4 * c + 3] = q4.w;
-    if constexpr (!kFromData) {
-      const float4 u4 = *reinterpret_cast<const float4*>(wu + g + 4 * c);
-      uu[4 * c] = u4.x;
-      uu[4 * c + 1] = u4.y;
-      uu[4 * c + 2] = u4.z;
-      uu[4 * c + 3] = u4.w;
-    }
-  }
-  if constexpr (kFromData) {
-#pragma unroll
-    for (int j = 0; j < S; ++j) v[j] = kk[j] < 0 ? 0.0f : qq[j];
-  } else {
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    int cur = -1;
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const int key = kk[j];
-      if (key >= 0 && key != cur) {
-        const double* m = x + 3 * static_cast<int64_t>(key);
-        m0 = m[0];
-        m1 = m[1];
-        m2 = m[2];
-        cur = key;
+    for (int c = 0; c < S / 4; ++c) {
+      const int4 k4 = *reinterpret_cast<const int4*>(lpix + g + 4 * c);
+      kk[4 * c] = k4.x;
+      kk[4 * c + 1] = k4.y;
+      kk[4 * c + 2] = k4.z;
+      kk[4 * c + 3] = k4.w;
+      const float4 q4 = *reinterpret_cast<const float4*>((kFromData ? d : wq) + g + 4 * c);
+      qq[4 * c] = q4.x;
+      qq[4 * c + 1] = q4.y;
+      qq[4 * c + 2] = q4.z;
+      qq[4 * c + 3] = q4.w;
+      if constexpr (!kFromData) {
+        const float4 u4 = *reinterpret_cast<const float4*>(wu + g + 4 * c);
+        uu[4 * c] = u4.x;
+        uu[4 * c + 1] = u4.y;
+        uu[4 * c + 2] = u4.z;
+        uu[4 * c + 3] = u4.w;
       }
-      v[j] = key < 0 ? 0.0f
-                     : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
-                                          static_cast<double>(uu[j]) * m2);
     }
   }
-}
+
+  // Scan runs keep a pixel for several consecutive samples, so a lane usually sees one or two
+  // pixels: it loads the pixels of its first and last samples together, behind a single wait,
+  // and goes back for a third pixel only when one occurs.
+  __device__ __forceinline__ void resolve(const double* __restrict__ x, float (&v)[S]) const {
+    if constexpr (kFromData) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) v[j] = kk[j] < 0 ? 0.0f : qq[j];
+    } else {
+      const int ka = kk[0], kb = kk[S - 1];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+      if (ka >= 0) {
+        const double* m = x + 3 * static_cast<int64_t>(ka);
+        a0 = m[0];
+        a1 = m[1];
+        a2 = m[2];
+      }
+      if (kb >= 0 && kb != ka) {
+        const double* m = x + 3 * static_cast<int64_t>(kb);
+        b0 = m[0];
+        b1 = m[1];
+        b2 = m[2];
+      }
+      bool other = false;
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const int key = kk[j];
+        const bool is_a = key == ka;
+        const double m0 = is_a ? a0 : b0, m1 = is_a ? a1 : b1, m2 = is_a ? a2 : b2;
+        other |= key >= 0 && key != ka && key != kb;
+        v[j] = key < 0 ? 0.0f
+                       : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
+                                            static_cast<double>(uu[j]) * m2);
+      }
+      if (other) {  // a third pixel inside the lane
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          const int key = kk[j];
+          if (key >= 0 && key != ka && key != kb) {
+            const double* m = x + 3 * static_cast<int64_t>(key);
+            v[j] = static_cast<float>(m[0] + static_cast<double>(qq[j]) * m[1] +
+                                      static_cast<double>(uu[j]) * m[2]);
+          }
+        }
+      }
+    }
+  }
+};
 
 template <int LOG, bool kFromData>
 __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
@@ -143,7 +167,9 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
     const int64_t g = in0 + n;
     float v[SG];
     if (g >= b0 && g + SG <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
-      gather_lane<SG, kFromData>(lpix, wq, wu, x, d, g, v);
+      LanePointing<SG, kFromData> lane;
+      lane.load(lpix, wq, wu, d, g);
+      lane.resolve(x, v);
     } else {
 #pragma unroll
       for (int j = 0; j < SG; ++j) {
@@ -174,22 +200,15 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
     int key[SS];
     double v[SS][3];
     if (i0 + SS <= c.out_len && (o & 3) == 0) {
+      LanePointing<SS, false> lane;
+      lane.load(lpix, wq, wu, nullptr, o);
 #pragma unroll
-      for (int cc = 0; cc < SS / 4; ++cc) {
-        const int4 k4 = *reinterpret_cast<const int4*>(lpix + o + 4 * cc);
-        const float4 q4 = *reinterpret_cast<const float4*>(wq + o + 4 * cc);
-        const float4 w4 = *reinterpret_cast<const float4*>(wu + o + 4 * cc);
-        const int kq[4] = {k4.x, k4.y, k4.z, k4.w};
-        const float qq[4] = {q4.x, q4.y, q4.z, q4.w};
-        const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double tv = real_out(buf, lam + i0 + 4 * cc + j);
-          key[4 * cc + j] = kq[j];
-          v[4 * cc + j][0] = tv;
-          v[4 * cc + j][1] = static_cast<double>(qq[j]) * tv;
-          v[4 * cc + j][2] = static_cast<double>(ww[j]) * tv;
-        }
+      for (int j = 0; j < SS; ++j) {
+        const double tv = real_out(buf, lam + i0 + j);
+        key[j] = lane.kk[j];
+        v[j][0] = tv;
+        v[j][1] = static_cast<double>(lane.qq[j]) * tv;
+        v[j][2] = static_cast<double>(lane.uu[j]) * tv;
       }
     } else {
 #pragma unroll

@@ -188,29 +188,62 @@ struct FftCfg {
 };
 
 
-// Real spectrum step between the two transforms: unpack the half-length spectrum of the N real
-// samples (packed as NC complex values), multiply by the band symbol S (already scaled by
-// 1/(2N)), repack for the inverse transform and store the conjugate (the inverse transform is
-// the conjugate of the forward transform of the conjugate).
+// Real spectrum step between the two transforms.  The N real samples are packed as NC complex
+// values z[m] = t[2m] + i t[2m+1] with transform Z; the step unpacks the real spectrum X at k
+// and NC - k, multiplies by the band symbol S (already scaled by 1/(2N)), repacks for the
+// inverse transform and stores the conjugate (the inverse transform is the conjugate of the
+// forward transform of the conjugate).  Written out, that chain of linear maps collapses to two
+// real coefficients per output: with W = exp(-2 pi i k / N) = c - i s, sigma = S[k] + S[NC-k]
+// and delta = S[k] - S[NC-k],
+//   Z'[k]    = 2 (sigma - delta s) conj(Z[k])    - 2 i delta c Z[NC-k]
+//   Z'[NC-k] = 2 (sigma + delta s) conj(Z[NC-k]) - 2 i delta c Z[k]
+// Each thread owns R = NC / (2T) pairs (k, NC - k), k = tid + r T, and thread 0 also the middle
+// bin k = NC/2.  The pairs are disjoint, so the loads of a batch of pairs (the symbol from
+// global memory, the spectrum from LDS) are all issued before its stores: one memory latency
+// per batch instead of one per pair.
 template <int LOG, int T>
 __device__ __forceinline__ void symbol_multiply(float2* buf, const float* __restrict__ S,
                                                 const float2* tw0, const float2* tw1) {
   constexpr int NC = 1 << LOG;
-  for (int k = threadIdx.x; k <= NC / 2; k += T) {
-    const int k2 = (NC - k) & (NC - 1);
-    const float2 Z = buf[pad(k)], Z2 = buf[pad(k2)];
-    const float2 E = make_float2(Z.x + Z2.x, Z.y - Z2.y);
-    const float2 O = make_float2(Z.y + Z2.y, Z2.x - Z.x);  // -i (Z - conj(Z2))
-    const float2 W = twiddle(tw0, tw1, k);
-    const float2 WO = cmul(W, O);
-    const float sa = S[k], sb = S[NC - k];
-    const float2 Ya = make_float2(sa * (E.x + WO.x), sa * (E.y + WO.y));
-    const float2 Yb = make_float2(sb * (E.x - WO.x), sb * (E.y - WO.y));
-    const float2 Ye = cadd(Ya, Yb);
-    const float2 Yo = cmulc(csub(Ya, Yb), W);
-    // Z'[k] = Ye + i Yo ; Z'[NC-k] = conj(Ye) + i conj(Yo); store conjugates.
-    buf[pad(k)] = make_float2(Ye.x - Yo.y, -(Ye.y + Yo.x));
-    if (k2 != k) buf[pad(k2)] = make_float2(Ye.x + Yo.y, Ye.y - Yo.x);
+  constexpr int R = NC / (2 * T);
+  constexpr int B = 4;  // pairs per batch
+  static_assert(R * 2 * T == NC && R % B == 0, "pairs per thread");
+  const int tid = threadIdx.x;
+  const float s_mid = tid == 0 ? S[NC / 2] : 0.0f;
+#pragma unroll
+  for (int r0 = 0; r0 < R; r0 += B) {
+    float sa[B], sb[B];
+    float2 Z[B], Z2[B], W[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int k = tid + (r0 + r) * T;
+      sa[r] = S[k];
+      sb[r] = S[NC - k];
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int k = tid + (r0 + r) * T;
+      Z[r] = buf[pad(k)];
+      Z2[r] = buf[pad((NC - k) & (NC - 1))];
+      W[r] = twiddle(tw0, tw1, k);
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int k = tid + (r0 + r) * T;
+      const int k2 = (NC - k) & (NC - 1);
+      const float a = 2.0f * sa[r], b = 2.0f * sb[r];
+      const float sig = a + b, del = a - b;
+      const float ds = del * W[r].y;  // -2 delta s
+      const float p = sig + ds, p2 = sig - ds, q = del * W[r].x;
+      buf[pad(k)] = make_float2(p * Z[r].x + q * Z2[r].y, -(p * Z[r].y + q * Z2[r].x));
+      if (k2 != k)  // k = 0 pairs with itself
+        buf[pad(k2)] = make_float2(p2 * Z2[r].x + q * Z[r].y, -(p2 * Z2[r].y + q * Z[r].x));
+    }
+  }
+  if (tid == 0) {  // k = NC/2: s = 1, c = 0, delta = 0
+    const float2 Z = buf[pad(NC / 2)];
+    const float p = 4.0f * s_mid;
+    buf[pad(NC / 2)] = make_float2(p * Z.x, -(p * Z.y));
   }
   __syncthreads();
 }

@@ -4,9 +4,9 @@
 // Layout: per-sample arrays are separate coalesced streams (local pixel int32, cos/sin FP32);
 // each thread owns 8 consecutive samples, read with two 16-byte loads per stream.  Pixel-domain
 // vectors are FP64 [n_kept][3] and stay cache-resident while the time streams go by; the
-// un-pointing loads a pixel's three values only when the pixel changes from the thread's
-// previous sample (scan runs make that rare), since these kernels are bound by the count of
-// vector memory instructions rather than by bytes.  P^T accumulates in FP64: samples of one
+// un-pointing loads the pixels of a thread's first and last samples together and a third pixel
+// only when one occurs (scan runs make that rare), since these kernels are bound by the count
+// and the latency of vector memory instructions rather than by bytes.  P^T accumulates in FP64: samples of one
 // pixel arrive in runs (the scan dwells on a pixel for several samples), so each thread first
 // sums its own run pieces, then a wavefront segmented scan merges runs that continue across
 // lanes, and only the lane that closes a run issues the three FP64 atomic adds.
@@ -51,20 +51,41 @@ __global__ __launch_bounds__(kThreads) void k_unpoint(const int32_t* __restrict_
         qq[4 * c] = q4.x; qq[4 * c + 1] = q4.y; qq[4 * c + 2] = q4.z; qq[4 * c + 3] = q4.w;
         uu[4 * c] = u4.x; uu[4 * c + 1] = u4.y; uu[4 * c + 2] = u4.z; uu[4 * c + 3] = u4.w;
       }
-      double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-      int cur = -1;
+      // the pixels of the first and last samples are loaded together behind one wait; a third
+      // pixel inside the lane (rare along scan runs) is loaded afterwards
+      const int ka = key[0], kb = key[kLane - 1];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+      if (ka >= 0) {
+        const double* m = x + 3 * static_cast<int64_t>(ka);
+        a0 = m[0];
+        a1 = m[1];
+        a2 = m[2];
+      }
+      if (kb >= 0 && kb != ka) {
+        const double* m = x + 3 * static_cast<int64_t>(kb);
+        b0 = m[0];
+        b1 = m[1];
+        b2 = m[2];
+      }
+      bool other = false;
 #pragma unroll
       for (int j = 0; j < kLane; ++j) {
-        if (key[j] >= 0 && key[j] != cur) {
-          const double* m = x + 3 * static_cast<int64_t>(key[j]);
-          m0 = m[0];
-          m1 = m[1];
-          m2 = m[2];
-          cur = key[j];
-        }
+        const bool is_a = key[j] == ka;
+        const double m0 = is_a ? a0 : b0, m1 = is_a ? a1 : b1, m2 = is_a ? a2 : b2;
+        other |= key[j] >= 0 && key[j] != ka && key[j] != kb;
         out[j] = key[j] < 0 ? 0.0f
                             : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
                                                  static_cast<double>(uu[j]) * m2);
+      }
+      if (other) {
+#pragma unroll
+        for (int j = 0; j < kLane; ++j) {
+          if (key[j] >= 0 && key[j] != ka && key[j] != kb) {
+            const double* m = x + 3 * static_cast<int64_t>(key[j]);
+            out[j] = static_cast<float>(m[0] + static_cast<double>(qq[j]) * m[1] +
+                                        static_cast<double>(uu[j]) * m[2]);
+          }
+        }
       }
 #pragma unroll
       for (int c = 0; c < kLane / 4; ++c)
