@@ -49,12 +49,25 @@ def log(*a):
 
 
 KERNEL_SOURCES = {
-    "apply_fused": ("apply_fused.hip", "fft_lds.h", "wave_runs.h"),
+    "apply_fused": ("apply_fused.hip", "fft_lds.h", "segment_io.h", "wave_runs.h"),
+    "apply_reg": ("apply_reg.hip", "fft_lds.h", "segment_io.h", "wave_runs.h"),
     "toeplitz": ("toeplitz.hip", "fft_lds.h"),
     "toeplitz_long": ("toeplitz_long.hip", "fft_lds.h"),
     "unpoint": ("pointing.hip",),
     "point": ("pointing.hip", "wave_runs.h"),
 }
+
+
+def fused_kernel(pinfo):
+    """Name of the fused product kernel a plan runs: register-resident FFT (2^15-sample
+    segments with at most 2^14 outputs) or LDS-resident FFT."""
+    return "apply_reg" if pinfo["fused"] == 2 else "apply_fused"
+
+
+def plan_flags(args):
+    from paper_2112_03370_amd import mapmaker as mm
+    return (mm.FLAG_UNFUSED if getattr(args, "unfused", False) else 0) | \
+        (mm.FLAG_LDS_FFT if getattr(args, "lds_fft", False) else 0)
 
 
 def kernel_source_hash(kernel):
@@ -141,7 +154,8 @@ def run_batched(args, prob, mm, torch, dev, stream):
     def step(block, timing=False):
         with torch.cuda.stream(stream):
             plan = mm.Plan(pix_d, wq_d, wu_d, prob.n_pix_global, prob.blk_start, prob.blk_len,
-                           prob.blk_band, prob.bands, det_offset=prob.det_offset, stream=stream)
+                           prob.blk_band, prob.bands, det_offset=prob.det_offset,
+                           flags=plan_flags(args), stream=stream)
             if timing:
                 plan.set_timing(True)
             x, infos = plan.pcg_solve(d, tol=args.tol, block=block, stream=stream)
@@ -189,7 +203,8 @@ def run_batched(args, prob, mm, torch, dev, stream):
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
             plan = mm.Plan(pix_d, wq_d, wu_d, prob.n_pix_global, prob.blk_start, prob.blk_len,
-                           prob.blk_band, prob.bands, det_offset=prob.det_offset, stream=stream)
+                           prob.blk_band, prob.bands, det_offset=prob.det_offset,
+                           flags=plan_flags(args), stream=stream)
             dinfo = plan.deflation_build(d[0], args.defl_m, stream=stream)
             x2, infos2 = plan.pcg_solve(d, tol=args.tol, precond=1, stream=stream)
             plan.close()
@@ -218,8 +233,8 @@ def run_batched(args, prob, mm, torch, dev, stream):
     hbm = 12.0 * n_s * cnt / (tot * 1e-3) / 1e9
     roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
-            "traffic": committed_traffic("apply_fused", "batched"),
-            "kernel": "apply_fused", "launches": cnt, "column_applies": col_applies,
+            "traffic": committed_traffic(fused_kernel(pinfo), "batched"),
+            "kernel": fused_kernel(pinfo), "launches": cnt, "column_applies": col_applies,
             "avg_launch_ms": round(tot / max(1, cnt), 4),
             "avg_ms_per_column_apply": round(tot / max(1, col_applies), 4),
             "pointing_hbm_gbs": round(hbm, 1), "pointing_hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
@@ -461,7 +476,7 @@ def run_serving(args, mm, torch, dev):
         "iterations_total": int(it_srv),
         "roofline": {"bound": "hbm", "achieved": round(agg, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(agg / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "apply_fused, aggregate over overlapping requests",
+                     "kernel": "fused products, aggregate over overlapping requests",
                      "tod_sample_products": int(samp_srv)},
         "cpu_baseline": cpu,
     }
@@ -475,6 +490,8 @@ def main():
     ap.add_argument("--config", default="ground", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lds-fft", action="store_true",
+                    help="keep 2^15-sample segments in the LDS-resident fused kernel")
     ap.add_argument("--unfused", action="store_true",
                     help="three-kernel FFT path (gather / Toeplitz / scatter) instead of fused")
     ap.add_argument("--block", type=int, default=-1,
@@ -523,7 +540,7 @@ def main():
             t0 = time.perf_counter()
             plan = mm.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
                            prob.blk_band, prob.bands, det_offset=prob.det_offset,
-                           flags=mm.FLAG_UNFUSED if args.unfused else 0, stream=stream)
+                           flags=plan_flags(args), stream=stream)
             t1 = time.perf_counter()
             if timing:
                 plan.set_timing(True)
@@ -564,7 +581,7 @@ def main():
     cnt = {k: sum(kt[k][1] for kt in kts) for k in range(4)}
     fused = bool(pinfo["fused"])
     toep = "toeplitz_long" if pinfo["fft_size"] > (1 << 15) else "toeplitz"
-    names = {0: "unpoint", 1: "apply_fused" if fused else toep, 2: "point", 3: "cg_vector"}
+    names = {0: "unpoint", 1: fused_kernel(pinfo) if fused else toep, 2: "point", 3: "cg_vector"}
     dom = max(range(3), key=lambda k: tot[k])
     avg_ms = tot[dom] / max(1, cnt[dom])
     # algorithmic bytes per sample and launch (one launch covers n_samples): pointing is 12 B

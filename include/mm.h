@@ -98,8 +98,11 @@ typedef struct {
 } mm_geometry;
 
 /* mm_geometry.flags: MM_FLAG_UNFUSED keeps the FFT path's gather, Toeplitz product and scatter
- * as three kernels with FP32 time-domain vectors in HBM (the fused kernel is the default). */
-enum { MM_FLAG_UNFUSED = 1 };
+ * as three kernels with FP32 time-domain vectors in HBM (the fused kernel is the default).
+ * MM_FLAG_LDS_FFT keeps fused 2^15-sample segments in the LDS-resident kernel (one workgroup
+ * per CU); by default segments of that length with at most 2^14 outputs (lambda >= 2^13) use
+ * the register-resident kernel, which runs two workgroups per CU. */
+enum { MM_FLAG_UNFUSED = 1, MM_FLAG_LDS_FFT = 2 };
 
 typedef struct {
   int64_t n_samples;
@@ -114,7 +117,8 @@ typedef struct {
   int32_t fft_size;       /* 0 when not using the FFT product */
   int32_t n_blocks;
   int32_t n_chunks;       /* overlap-save segments (FFT) or tiles (direct) per product */
-  int32_t fused;          /* 1: gather, Toeplitz and scatter run as one kernel per segment */
+  int32_t fused;          /* 1: gather, Toeplitz and scatter run as one kernel per segment
+                             (LDS-resident FFT), 2: the same with the register-resident FFT */
 } mm_plan_info_t;
 
 typedef struct {

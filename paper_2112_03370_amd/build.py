@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmm.so")
-SOURCES = ["api.hip", "plan.hip", "pointing.hip", "toeplitz.hip", "toeplitz_long.hip", "apply_fused.hip", "cg.hip", "block.hip", "server.hip",
+SOURCES = ["api.hip", "plan.hip", "pointing.hip", "toeplitz.hip", "toeplitz_long.hip", "apply_fused.hip", "apply_reg.hip", "cg.hip", "block.hip", "server.hip",
            "deflation.hip"]
 
 FLAGS = [

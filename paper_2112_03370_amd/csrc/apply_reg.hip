@@ -1,0 +1,447 @@
+// Fused system product for 2^15-sample overlap-save segments with a register-resident FFT.
+//
+// Same operation as the LDS-resident fused kernel (gather t = P x, Toeplitz u = N^-1 t by the
+// real FFT of the segment, scatter y += P^T u over the segment's outputs), laid out so that
+// two workgroups share a CU: 512 threads each hold 32 of the 16,384 complex points in
+// registers, and LDS (about 75 KB per workgroup) only stages the gather, the transposes between
+// the three radix steps and the outputs.  While one workgroup waits on its gather or scatter
+// the other keeps the vector ALUs busy with its transforms, which a single 142 KB workgroup
+// per CU cannot do.
+//
+// Transform (NC = 16384 points z[n] = t[2n] + i t[2n+1], n = n1 + 16 n2 + 512 j,
+// k = k3 + 32 k2 + 1024 k1):
+//   A  thread t = n1 + 16 n2 holds z[t + 512 j], j < 32: radix-32 over j, twiddle W_NC^(t k3)
+//   B  thread (k3, n1) holds slot n2:                  radix-32 over n2, twiddle W_512^(n1 k2)
+//   C  thread holds two tasks (k3, k2), slot n1:       radix-16 over n1 -> Z[k], k1 < 16
+// The two tasks of a thread are chosen so that the partner bin NC - k of each of its bins is
+// also in the thread, so the real-spectrum step (unpack, band symbol, repack) stays in
+// registers.  The inverse runs the same steps transposed (C, B, A with the same twiddles):
+// the transposed factorisation of the symmetric DFT matrix is the DFT again, so it maps the
+// repacked spectrum back to the natural order that the first step read.
+#include "fft_lds.h"
+#include "mm_internal.h"
+#include "segment_io.h"
+#include "wave_runs.h"
+
+namespace mm {
+
+namespace {
+
+using namespace fft;
+
+constexpr int kT = 512;            // threads per workgroup
+constexpr int kNC = 16384;         // complex points per segment
+constexpr int kN = 2 * kNC;        // real samples per segment
+constexpr int kHalf = kNC;         // window samples staged per gather half; outputs at most
+constexpr int kRowA = 528;         // LDS stride of a k3 row in the A <-> B transposes
+constexpr int kRowB = 544;         // LDS stride of a k3 plane in the B <-> C transposes
+constexpr int kLdsF = 32 * kRowB;  // floats of staging LDS
+constexpr int kLane = 8;           // consecutive samples per lane in the gather and scatter
+
+// cos and sin of 2 pi k / 32, k < 16
+__device__ constexpr float kCos32[16] = {
+    1.0f, 0.98078528040323043f, 0.92387953251128674f, 0.83146961230254524f,
+    0.70710678118654752f, 0.55557023301960218f, 0.38268343236508978f, 0.19509032201612827f,
+    0.0f, -0.19509032201612827f, -0.38268343236508978f, -0.55557023301960218f,
+    -0.70710678118654752f, -0.83146961230254524f, -0.92387953251128674f, -0.98078528040323043f};
+__device__ constexpr float kSin32[16] = {
+    0.0f, 0.19509032201612827f, 0.38268343236508978f, 0.55557023301960218f,
+    0.70710678118654752f, 0.83146961230254524f, 0.92387953251128674f, 0.98078528040323043f,
+    1.0f, 0.98078528040323043f, 0.92387953251128674f, 0.83146961230254524f,
+    0.70710678118654752f, 0.55557023301960218f, 0.38268343236508978f, 0.19509032201612827f};
+
+// Radix-32 DFT on v[0..32) in natural order: two radix-16 DFTs (even and odd points) and a
+// radix-2 step with W_32^k.
+__device__ __forceinline__ void dft32(float2 (&v)[32]) {
+  float2 e[16], o[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    e[i] = v[2 * i];
+    o[i] = v[2 * i + 1];
+  }
+  dft<16>(e);
+  dft<16>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float2 E = e[out_slot<16>(k)];
+    float2 O = o[out_slot<16>(k)];
+    if (k == 8)
+      O = mul_mi(O);
+    else if (k != 0)
+      O = cmul(O, make_float2(kCos32[k], -kSin32[k]));
+    v[k] = cadd(E, O);
+    v[k + 16] = csub(E, O);
+  }
+}
+
+// Radix-16 DFT on v[off..off+16) in natural order.
+template <int OFF>
+__device__ __forceinline__ void dft16_at(float2 (&v)[32]) {
+  float2 u[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) u[i] = v[OFF + i];
+  dft<16>(u);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[OFF + k] = u[out_slot<16>(k)];
+}
+
+// v[k] *= W_NC^(t k) = W_N^(2 t k), k < 32, from five table twiddles and their products
+// (2 t k < 2^15 for t < 512: no reduction of the angle index).
+__device__ __forceinline__ void twiddle_a(float2 (&v)[32], int t, const float2* tw0,
+                                          const float2* tw1) {
+  const float2 w1 = twiddle(tw0, tw1, 2 * t), w2 = twiddle(tw0, tw1, 4 * t);
+  const float2 w4 = twiddle(tw0, tw1, 8 * t), w8 = twiddle(tw0, tw1, 16 * t);
+  const float2 w16 = twiddle(tw0, tw1, 32 * t);
+  float2 lo[8];
+  lo[0] = make_float2(1.0f, 0.0f);
+  lo[1] = w1;
+  lo[2] = w2;
+  lo[3] = cmul(w1, w2);
+  lo[4] = w4;
+  lo[5] = cmul(w1, w4);
+  lo[6] = cmul(w2, w4);
+  lo[7] = cmul(lo[3], w4);
+  const float2 hi[4] = {make_float2(1.0f, 0.0f), w8, w16, cmul(w8, w16)};
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      const int k = 8 * h + l;
+      if (k == 0) continue;
+      const float2 w = h == 0 ? lo[l] : (l == 0 ? hi[h] : cmul(hi[h], lo[l]));
+      v[k] = cmul(v[k], w);
+    }
+  }
+}
+
+template <int C>
+__device__ __forceinline__ float& part(float2& z) {
+  if constexpr (C == 0) return z.x;
+  else return z.y;
+}
+
+// A layout (thread t, slot k3) -> B layout (thread (k3, n1), slot n2), one component.
+template <int C>
+__device__ __forceinline__ void transpose_ab(float2 (&v)[32], float* lds, int tid, int k3b,
+                                            int n1b) {
+#pragma unroll
+  for (int k = 0; k < 32; ++k) lds[k * kRowA + tid] = part<C>(v[k]);
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 32; ++n2) part<C>(v[n2]) = lds[k3b * kRowA + n1b + 16 * n2];
+  __syncthreads();
+}
+
+// B layout -> A layout.
+template <int C>
+__device__ __forceinline__ void transpose_ba(float2 (&v)[32], float* lds, int tid, int k3b,
+                                            int n1b) {
+#pragma unroll
+  for (int n2 = 0; n2 < 32; ++n2) lds[k3b * kRowA + n1b + 16 * n2] = part<C>(v[n2]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; ++k) part<C>(v[k]) = lds[k * kRowA + tid];
+  __syncthreads();
+}
+
+// Task slots of the B <-> C transposes: plane k3, row k2 of 17 floats, column n1.
+struct Tasks {
+  int a, b;  // k3 * kRowB + 17 * k2 of the two tasks
+};
+
+// B layout (thread (k3, n1), slot k2) -> C layout (tasks a, b; slots n1 and 16 + n1).
+template <int C>
+__device__ __forceinline__ void transpose_bc(float2 (&v)[32], float* lds, Tasks tk, int k3b,
+                                            int n1b) {
+#pragma unroll
+  for (int k2 = 0; k2 < 32; ++k2) lds[k3b * kRowB + 17 * k2 + n1b] = part<C>(v[k2]);
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    part<C>(v[n1]) = lds[tk.a + n1];
+    part<C>(v[16 + n1]) = lds[tk.b + n1];
+  }
+  __syncthreads();
+}
+
+// C layout -> B layout.
+template <int C>
+__device__ __forceinline__ void transpose_cb(float2 (&v)[32], float* lds, Tasks tk, int k3b,
+                                            int n1b) {
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    lds[tk.a + n1] = part<C>(v[n1]);
+    lds[tk.b + n1] = part<C>(v[16 + n1]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < 32; ++k2) part<C>(v[k2]) = lds[k3b * kRowB + 17 * k2 + n1b];
+  __syncthreads();
+}
+
+// Real-spectrum step for one bin pair: X1 = Z[k], X2 = Z[NC - k] (indices mod NC), sa = S[k],
+// sb = S[NC - k], W = W_N^k; the repacked, conjugated inverse input replaces both (see
+// symbol_multiply in the LDS kernels for the derivation).
+__device__ __forceinline__ void spectrum_pair(float2& X1, float2& X2, float sa, float sb,
+                                              float2 W) {
+  const float a = 2.0f * sa, b = 2.0f * sb;
+  const float sig = a + b, del = a - b;
+  const float ds = del * W.y;
+  const float p = sig + ds, p2 = sig - ds, q = del * W.x;
+  const float2 y1 = make_float2(p * X1.x + q * X2.y, -(p * X1.y + q * X2.x));
+  const float2 y2 = make_float2(p2 * X2.x + q * X1.y, -(p2 * X2.y + q * X1.x));
+  X1 = y1;
+  X2 = y2;
+}
+
+// A bin that is its own partner (k = 0 or NC/2).
+__device__ __forceinline__ void spectrum_self(float2& X, float sa, float sb, float2 W) {
+  const float a = 2.0f * sa, b = 2.0f * sb;
+  const float sig = a + b, del = a - b;
+  const float p = sig + del * W.y, q = del * W.x;
+  X = make_float2(p * X.x + q * X.y, -(p * X.y + q * X.x));
+}
+
+template <bool kFromData>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_apply_reg(
+    const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
+    const double* __restrict__ x0, const float* __restrict__ d0, int d_vec, double* __restrict__ y0,
+    int ncol, int64_t ldx, int64_t ldy, const Chunk* __restrict__ chunks,
+    const float* __restrict__ spec, const float2* __restrict__ tw0g,
+    const float2* __restrict__ tw1g, int lam, const int32_t* __restrict__ done) {
+  __shared__ __align__(16) float lds[kLdsF + 64];
+  __shared__ float2 tw0[128];
+  __shared__ float2 tw1[kN / 128];
+  __shared__ float2 w512[512];  // W_512^j = W_N^(64 j)
+  if (done != nullptr && *done) return;
+  const int tid = threadIdx.x;
+  if (tid < 128) tw0[tid] = tw0g[tid];
+  if (tid < kN / 128) tw1[tid] = tw1g[tid];
+  w512[tid] = cmul(tw1g[tid >> 1], tw0g[(tid & 1) * 64]);
+
+  const int wg = xcd_ordered(blockIdx.x, gridDim.x);
+  const int col = wg % ncol;
+  const Chunk c = chunks[wg / ncol];
+  const double* __restrict__ x = kFromData ? x0 : x0 + col * ldx;
+  const float* __restrict__ d = kFromData ? d0 + col * ldx : d0;
+  double* __restrict__ y = y0 + col * ldy;
+  const int64_t in0 = c.out0 - lam;
+  const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
+
+  // thread roles: A layout t = tid; B layout (k3, n1); C layout two mirror tasks
+  const int k3b = tid >> 4, n1b = tid & 15;
+  int a3, a2, b3, b2;
+  if (tid >= 32) {
+    a3 = tid >> 5;
+    a2 = tid & 31;
+    b3 = 32 - a3;
+    b2 = 31 - a2;
+  } else if (tid >= 16) {
+    a3 = 16;
+    a2 = tid - 16;
+    b3 = 16;
+    b2 = 47 - tid;
+  } else {
+    a3 = 0;
+    a2 = tid;
+    b3 = 0;
+    b2 = tid == 0 ? 16 : 32 - tid;
+  }
+  const Tasks tk{a3 * kRowB + 17 * a2, b3 * kRowB + 17 * b2};
+
+  float2 v[32];
+
+  // ---- gather the window in two halves of 16,384 samples through LDS ----------------------
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int n = tid * kLane; n < kHalf; n += kT * kLane) {
+      const int64_t g = in0 + h * kHalf + n;
+      float s[kLane];
+      if (g >= b0 && g + kLane <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
+        LanePointing<kLane, kFromData> lane;
+        lane.load(lpix, wq, wu, d, g);
+        lane.resolve(x, s);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kLane; ++j) {
+          const int64_t gj = g + j;
+          s[j] = 0.0f;
+          if (gj >= b0 && gj < b1)
+            s[j] = gather_one<kFromData>(lpix[gj], wq[gj], wu[gj], x, kFromData ? d[gj] : 0.0f);
+        }
+      }
+      *reinterpret_cast<float4*>(lds + n) = make_float4(s[0], s[1], s[2], s[3]);
+      *reinterpret_cast<float4*>(lds + n + 4) = make_float4(s[4], s[5], s[6], s[7]);
+    }
+    __syncthreads();
+    // z[t + 512 j] = (t[2m], t[2m+1]), m = t + 512 j, j in [16 h, 16 h + 16)
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+      v[16 * h + jj] = *reinterpret_cast<const float2*>(lds + 2 * (tid + kT * jj));
+    __syncthreads();
+  }
+
+  // ---- forward transform --------------------------------------------------------------------
+  dft32(v);
+  twiddle_a(v, tid, tw0, tw1);
+  transpose_ab<0>(v, lds, tid, k3b, n1b);
+  transpose_ab<1>(v, lds, tid, k3b, n1b);
+  dft32(v);
+#pragma unroll
+  for (int k2 = 1; k2 < 32; ++k2) v[k2] = cmul(v[k2], w512[n1b * k2]);
+  transpose_bc<0>(v, lds, tk, k3b, n1b);
+  transpose_bc<1>(v, lds, tk, k3b, n1b);
+  dft16_at<0>(v);
+  dft16_at<16>(v);
+
+  // ---- real spectrum x band symbol, in registers --------------------------------------------
+  // Slot k1 of task a is bin k = a3 + 32 a2 + 1024 k1 and its partner NC - k is slot 15 - k1 of
+  // task b, for every thread but the first, whose tasks (0, 0) and (0, 16) are their own
+  // partners.  All threads run the common pairing; thread 0 keeps its spectrum in a private LDS
+  // slot and redoes its bins from there, which keeps the common path free of a second register
+  // pairing.
+  {
+    const float* __restrict__ S = spec + static_cast<int64_t>(c.band) * (kNC + 1);
+    float2* own = reinterpret_cast<float2*>(lds + kLdsF);  // thread 0 only; the transposes never
+                                                            // reach past kLdsF
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) own[i] = v[i];
+    }
+    const int ka = a3 + 32 * a2;
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {  // symbol loads of four pairs behind one wait
+      float sa[4], sb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = ka + 1024 * (k0 + r);
+        sa[r] = S[k];
+        sb[r] = S[kNC - k];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k1 = k0 + r;
+        spectrum_pair(v[k1], v[31 - k1], sa[r], sb[r], twiddle(tw0, tw1, ka + 1024 * k1));
+      }
+    }
+    if (tid == 0) {
+      // task (0, 0): bins 1024 k1, partners k1 <-> 16 - k1, bins 0 and NC/2 alone;
+      // task (0, 16): bins 512 + 1024 k1, partners k1 <-> 15 - k1
+      spectrum_self(own[0], S[0], S[kNC], twiddle(tw0, tw1, 0));
+      spectrum_self(own[8], S[kNC / 2], S[kNC / 2], twiddle(tw0, tw1, kNC / 2));
+#pragma unroll 1
+      for (int k1 = 1; k1 < 8; ++k1)
+        spectrum_pair(own[k1], own[16 - k1], S[1024 * k1], S[kNC - 1024 * k1],
+                      twiddle(tw0, tw1, 1024 * k1));
+#pragma unroll 1
+      for (int k1 = 0; k1 < 8; ++k1) {
+        const int k = 512 + 1024 * k1;
+        spectrum_pair(own[16 + k1], own[31 - k1], S[k], S[kNC - k], twiddle(tw0, tw1, k));
+      }
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = own[i];
+    }
+  }
+
+  // ---- inverse: the transposed steps --------------------------------------------------------
+  dft16_at<0>(v);
+  dft16_at<16>(v);
+#pragma unroll
+  for (int n1 = 1; n1 < 16; ++n1) {
+    v[n1] = cmul(v[n1], w512[n1 * a2]);
+    v[16 + n1] = cmul(v[16 + n1], w512[n1 * b2]);
+  }
+  transpose_cb<0>(v, lds, tk, k3b, n1b);
+  transpose_cb<1>(v, lds, tk, k3b, n1b);
+  dft32(v);
+  transpose_ba<0>(v, lds, tid, k3b, n1b);
+  transpose_ba<1>(v, lds, tid, k3b, n1b);
+  twiddle_a(v, tid, tw0, tw1);
+  dft32(v);
+
+  // ---- outputs to LDS: sample 2m is Re, 2m+1 is -Im of point m = t + 512 j ------------------
+  const int out_len = c.out_len;
+  if ((lam & 1) == 0) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const int i = 2 * (tid + kT * j) - lam;  // even
+      if (i >= 0 && i + 1 < out_len) {
+        *reinterpret_cast<float2*>(lds + i) = make_float2(v[j].x, -v[j].y);
+      } else if (i >= 0 && i < out_len) {
+        lds[i] = v[j].x;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const int i = 2 * (tid + kT * j) - lam;
+      if (i >= 0 && i < out_len) lds[i] = v[j].x;
+      if (i + 1 >= 0 && i + 1 < out_len) lds[i + 1] = -v[j].y;
+    }
+  }
+  __syncthreads();
+
+  // ---- scatter the segment's outputs ----------------------------------------------------------
+  const AtomicFlush flush{y};
+  for (int base = 0; base < out_len; base += kT * kLane) {  // same trip count for every lane
+    const int i0 = base + tid * kLane;
+    const int64_t o = c.out0 + i0;
+    int key[kLane];
+    double val[kLane][3];
+    if (i0 + kLane <= out_len && (o & 3) == 0) {
+      LanePointing<kLane, false> lane;
+      lane.load(lpix, wq, wu, nullptr, o);
+#pragma unroll
+      for (int j = 0; j < kLane; ++j) {
+        const double tv = lds[i0 + j];
+        key[j] = lane.kk[j];
+        val[j][0] = tv;
+        val[j][1] = static_cast<double>(lane.qq[j]) * tv;
+        val[j][2] = static_cast<double>(lane.uu[j]) * tv;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kLane; ++j) {
+        key[j] = -1;
+        val[j][0] = val[j][1] = val[j][2] = 0.0;
+        if (i0 + j < out_len) {
+          const int64_t oj = o + j;
+          key[j] = lpix[oj];
+          const double tv = lds[i0 + j];
+          val[j][0] = tv;
+          val[j][1] = static_cast<double>(wq[oj]) * tv;
+          val[j][2] = static_cast<double>(wu[oj]) * tv;
+        }
+      }
+    }
+    wave_merge_runs_n<kLane, 3>(key, val, flush);
+  }
+}
+
+}  // namespace
+
+bool apply_reg_supported(const Plan* P) {
+  return P->fft_n == kN && P->fft_n - 2 * static_cast<int64_t>(P->lambda_max) <= kHalf;
+}
+
+mm_status launch_apply_reg(Plan* P, const double* x, const float* d, int64_t ldx, double* y,
+                           int64_t ldy, int32_t ncol, const int32_t* done, hipStream_t s) {
+  if (!apply_reg_supported(P)) return fail(MM_ERR_UNSUPPORTED, "register FFT kernel: segment shape");
+  const bool vec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 && (ldx & 3) == 0;
+  const int d_vec = vec ? 1 : 0;
+  const int64_t grid = static_cast<int64_t>(P->n_chunks) * ncol;
+  if (grid > INT32_MAX) return fail(MM_ERR_UNSUPPORTED, "too many segment x column workgroups");
+  if (d != nullptr) {
+    hipLaunchKernelGGL((k_apply_reg<true>), dim3(static_cast<unsigned>(grid)), dim3(kT), 0, s,
+                       P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks, P->spec,
+                       P->tw0, P->tw1, P->lambda_max, done);
+  } else {
+    hipLaunchKernelGGL((k_apply_reg<false>), dim3(static_cast<unsigned>(grid)), dim3(kT), 0, s,
+                       P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks, P->spec,
+                       P->tw0, P->tw1, P->lambda_max, done);
+  }
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace mm

@@ -175,6 +175,7 @@ struct Plan {
   Tile* id_tiles = nullptr;     // the tiles of samples outside every block (weight 1)
   int32_t n_id_tiles = 0;
   bool fused = true;            // FFT path: gather + Toeplitz + scatter in one kernel
+  bool reg_fft = false;         // fused 2^15 segments in the register-resident kernel
   std::atomic<int32_t> tuned_block{0};  // block size chosen by a tuned stacked solve (0: none)
   int32_t n_chunks = 0;
   int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
@@ -241,6 +242,10 @@ mm_status launch_diag_tiles(Plan* P, const Tile* tiles, int32_t n_tiles, const d
 mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
                              const int32_t* done, hipStream_t s, int32_t ncol = 1,
                              int64_t ldx = 0, int64_t ldy = 0);
+// Register-resident variant for 2^15-sample segments with at most 2^14 outputs (apply_reg.hip).
+bool apply_reg_supported(const Plan* P);
+mm_status launch_apply_reg(Plan* P, const double* x, const float* d, int64_t ldx, double* y,
+                           int64_t ldy, int32_t ncol, const int32_t* done, hipStream_t s);
 mm_status launch_zero(double* y, int64_t n, hipStream_t s);
 
 // b = P^T N^-1 d (b overwritten).

@@ -744,6 +744,8 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   // ---- workspace -----------------------------------------------------------------------------
   if (algo == MM_TOEPLITZ_FFT && long_fft_size(fft_n))
     P->fused = false;  // long segments: gather, four-step product and scatter as three kernels
+  P->reg_fft = algo == MM_TOEPLITZ_FFT && P->fused && (g->flags & MM_FLAG_LDS_FFT) == 0 &&
+               apply_reg_supported(P);
   MM_TRY(work_alloc(P, &P->work));
   P->device_bytes += P->work.bytes;
 

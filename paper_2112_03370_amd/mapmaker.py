@@ -25,6 +25,7 @@ STATUS = {
 }
 TOEPLITZ_AUTO, TOEPLITZ_DIRECT, TOEPLITZ_FFT = 0, 1, 2
 FLAG_UNFUSED = 1
+FLAG_LDS_FFT = 2
 KIND_UNPOINT, KIND_TOEPLITZ, KIND_POINT, KIND_CG = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p

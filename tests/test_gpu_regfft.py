@@ -1,0 +1,90 @@
+"""GPU register-resident FFT segment kernel (2^15-sample segments with at most 2^14 outputs,
+i.e. lambda >= 2^13) through the C ABI.
+
+It computes the same system product as the LDS-resident fused kernel, so the bars are the same:
+relative L2 3e-6 against the FP64 oracle for A x and b = P^T N^-1 d (FP32 time domain), the two
+kernels within that bound of each other, and the PCG map within 1e-6 of the oracle's map.
+Cases: lambda 8192 with the automatic 2^15 length, odd lambda 8193 with the length forced
+(odd output offset, 16,382 outputs per segment), lambda 12000 (8,768 outputs), odd block
+lengths (ragged last segments), flagged samples (zero rows of P), and two columns at once.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+CASES = {
+    "lam8192": (dict(cfg_id=41, n_dets=3, samples_per_det=120001, interval=50021, side=40,
+                     lam=8192, flag_frac=0.02), {}),
+    "lam8193_forced": (dict(cfg_id=42, n_dets=2, samples_per_det=100003, interval=65536, side=40,
+                            lam=8193, flag_frac=0.01), dict(fft_size=32768)),
+    "lam12000": (dict(cfg_id=43, n_dets=2, samples_per_det=90007, interval=45001, side=32,
+                      lam=12000, flag_frac=0.0), {}),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        gkw, pkw = CASES[name]
+        prob = synth.make_ground(n_rhs=2, **gkw)
+        _cache[name] = (prob, O.plan_from_problem(prob), pkw)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_register_kernel_products_match_oracle(gpu_lib, name):
+    prob, ref, pkw = case(name)
+    plan = gpu_lib.Plan.from_problem(prob, **pkw)
+    assert plan.info["fused"] == 2 and plan.info["fft_size"] == 32768, plan.info
+    lds = gpu_lib.Plan.from_problem(prob, flags=gpu_lib.FLAG_LDS_FFT, **pkw)
+    assert lds.info["fused"] == 1
+    x = np.random.default_rng(11).standard_normal((2, ref.n_kept, 3))
+    y = plan.apply_A(_dev(x)).cpu().numpy()
+    y_lds = lds.apply_A(_dev(x)).cpu().numpy()
+    for j in range(2):
+        want = O.apply_A(ref, x[j])
+        err = float(_rel(y[j], want))
+        assert err <= 3e-6, (j, err)
+        assert float(_rel(y[j], y_lds[j])) <= 3e-6
+    for j in range(2):
+        b = plan.rhs(_dev(prob.d[j])).cpu().numpy()
+        err = float(_rel(b, O.rhs(ref, prob.d[j])))
+        assert err <= 3e-6, (j, err)
+
+
+def test_register_kernel_pcg_map(gpu_lib):
+    prob, ref, pkw = case("lam8192")
+    plan = gpu_lib.Plan.from_problem(prob, **pkw)
+    want = O.pcg(ref, O.rhs(ref, prob.d[0]), tol=1e-8)
+    x, info = plan.pcg_solve(_dev(prob.d[0]), tol=1e-8)
+    assert info["converged"] == 1 and info["true_relres"] < 1e-7, info
+    err = float(_rel(x.cpu().numpy(), want.x))
+    assert err <= 1e-6, err
+    assert abs(info["iterations"] - want.iterations) <= 3, (info["iterations"], want.iterations)
+
+
+def test_lds_flag_keeps_other_shapes(gpu_lib):
+    # lambda < 2^13 at length 2^15 has more than 2^14 outputs per segment: LDS kernel
+    prob = synth.make_ground(cfg_id=44, n_dets=2, samples_per_det=70001, interval=40001, side=24,
+                             lam=5000)
+    plan = gpu_lib.Plan.from_problem(prob)
+    assert plan.info["fft_size"] == 32768 and plan.info["fused"] == 1, plan.info
