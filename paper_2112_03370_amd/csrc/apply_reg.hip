@@ -37,6 +37,36 @@ constexpr int kRowA = 528;         // LDS stride of a k3 row in the A <-> B tran
 constexpr int kRowB = 544;         // LDS stride of a k3 plane in the B <-> C transposes
 constexpr int kLdsF = 32 * kRowB;  // floats of staging LDS
 constexpr int kLane = 8;           // consecutive samples per lane in the gather and scatter
+constexpr int kTab = 16 * kT + 8;  // symbol pairs per band in the kernel's read order
+
+typedef __attribute__((address_space(1))) const void* global_ptr;
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Direct load of 16 B per lane from global memory into LDS at (wave-uniform) wave_base +
+// 16 B x lane, without passing through registers.
+__device__ __forceinline__ void load_to_lds16(const void* src, void* wave_base) {
+  __builtin_amdgcn_global_load_lds((global_ptr)src, (lds_ptr)wave_base, 16, 0, 0);
+}
+
+// Tasks of a thread in the C layout: (a3, a2) and its mirror (b3, b2).
+__device__ __forceinline__ void reg_tasks(int tid, int& a3, int& a2, int& b3, int& b2) {
+  if (tid >= 32) {
+    a3 = tid >> 5;
+    a2 = tid & 31;
+    b3 = 32 - a3;
+    b2 = 31 - a2;
+  } else if (tid >= 16) {
+    a3 = 16;
+    a2 = tid - 16;
+    b3 = 16;
+    b2 = 47 - tid;
+  } else {
+    a3 = 0;
+    a2 = tid;
+    b3 = 0;
+    b2 = tid == 0 ? 16 : 32 - tid;
+  }
+}
 
 // cos and sin of 2 pi k / 32, k < 16
 __device__ constexpr float kCos32[16] = {
@@ -207,7 +237,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
     const double* __restrict__ x0, const float* __restrict__ d0, int d_vec, double* __restrict__ y0,
     int ncol, int64_t ldx, int64_t ldy, const Chunk* __restrict__ chunks,
-    const float* __restrict__ spec, const float2* __restrict__ tw0g,
+    const float2* __restrict__ tab, const float2* __restrict__ tw0g,
     const float2* __restrict__ tw1g, int lam, const int32_t* __restrict__ done) {
   __shared__ __align__(16) float lds[kLdsF + 64];
   __shared__ float2 tw0[128];
@@ -231,22 +261,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // thread roles: A layout t = tid; B layout (k3, n1); C layout two mirror tasks
   const int k3b = tid >> 4, n1b = tid & 15;
   int a3, a2, b3, b2;
-  if (tid >= 32) {
-    a3 = tid >> 5;
-    a2 = tid & 31;
-    b3 = 32 - a3;
-    b2 = 31 - a2;
-  } else if (tid >= 16) {
-    a3 = 16;
-    a2 = tid - 16;
-    b3 = 16;
-    b2 = 47 - tid;
-  } else {
-    a3 = 0;
-    a2 = tid;
-    b3 = 0;
-    b2 = tid == 0 ? 16 : 32 - tid;
-  }
+  reg_tasks(tid, a3, a2, b3, b2);
   const Tasks tk{a3 * kRowB + 17 * a2, b3 * kRowB + 17 * b2};
 
   float2 v[32];
@@ -291,57 +306,81 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int k2 = 1; k2 < 32; ++k2) v[k2] = cmul(v[k2], w512[n1b * k2]);
   transpose_bc<0>(v, lds, tk, k3b, n1b);
   transpose_bc<1>(v, lds, tk, k3b, n1b);
+  // The band's symbol pairs (kTab float2, in this kernel's read order) go straight from global
+  // memory into the idle staging LDS while the radix-16 steps run: each wave's direct load of
+  // 16 B per lane lands at its wave base + 16 B x lane.
+  {
+    const float4* __restrict__ tg = reinterpret_cast<const float4*>(tab + c.band * kTab);
+    const int wbase = tid & ~63;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      load_to_lds16(tg + r * kT + tid, lds + 4 * (r * kT + wbase));
+    if (tid < (2 * kTab) / 4 - 8 * kT)
+      load_to_lds16(tg + 8 * kT + tid, lds + 4 * 8 * kT);
+  }
   dft16_at<0>(v);
   dft16_at<16>(v);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
   // ---- real spectrum x band symbol, in registers --------------------------------------------
   // Slot k1 of task a is bin k = a3 + 32 a2 + 1024 k1 and its partner NC - k is slot 15 - k1 of
   // task b, for every thread but the first, whose tasks (0, 0) and (0, 16) are their own
   // partners.  All threads run the common pairing; thread 0 keeps its spectrum in a private LDS
-  // slot and redoes its bins from there, which keeps the common path free of a second register
-  // pairing.
+  // slot, where lanes 0..16 of its wave redo its 17 bin pairs (two of them single bins) side by
+  // side, and reloads it after the common pairing.  That keeps the common path free of a second
+  // register pairing.  The slot is written and read by one wave only, whose LDS operations
+  // complete in order.  (The side work comes before the common pairing: placed after it, the
+  // compiler's schedule no longer fits the 128 registers of two workgroups per CU.)
   {
-    const float* __restrict__ S = spec + static_cast<int64_t>(c.band) * (kNC + 1);
+    const float2* stab = reinterpret_cast<const float2*>(lds);  // [k1][thread], then 8 extra
     float2* own = reinterpret_cast<float2*>(lds + kLdsF);  // thread 0 only; the transposes never
                                                             // reach past kLdsF
     if (tid == 0) {
 #pragma unroll
       for (int i = 0; i < 32; ++i) own[i] = v[i];
     }
+    if (tid < 17) {
+      // task (0, 0): bins 1024 k1, partners k1 <-> 16 - k1, bins 0 and NC/2 alone (lanes 0..8);
+      // task (0, 16): bins 512 + 1024 k1, partners k1 <-> 15 - k1 (lanes 9..16)
+      int i1, i2, k, e;
+      if (tid == 0) {
+        i1 = i2 = 0;
+        k = 0;
+        e = 0;
+      } else if (tid == 1) {
+        i1 = i2 = 8;
+        k = kNC / 2;
+        e = 8 * kT;
+      } else if (tid <= 8) {
+        i1 = tid - 1;
+        i2 = 17 - tid;
+        k = 1024 * i1;
+        e = i1 * kT;
+      } else {
+        i1 = tid + 7;
+        i2 = 40 - tid;
+        k = 512 + 1024 * (tid - 9);
+        e = 16 * kT + tid - 9;
+      }
+      float2 X1 = own[i1], X2 = own[i2];
+      const float2 ss = stab[e];
+      spectrum_pair(X1, X2, ss.x, ss.y, twiddle(tw0, tw1, k));
+      own[i1] = X1;
+      if (i2 != i1) own[i2] = X2;
+    }
     const int ka = a3 + 32 * a2;
 #pragma unroll
-    for (int k0 = 0; k0 < 16; k0 += 4) {  // symbol loads of four pairs behind one wait
-      float sa[4], sb[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = ka + 1024 * (k0 + r);
-        sa[r] = S[k];
-        sb[r] = S[kNC - k];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k1 = k0 + r;
-        spectrum_pair(v[k1], v[31 - k1], sa[r], sb[r], twiddle(tw0, tw1, ka + 1024 * k1));
-      }
+    for (int k1 = 0; k1 < 16; ++k1) {
+      const float2 ss = stab[k1 * kT + tid];
+      spectrum_pair(v[k1], v[31 - k1], ss.x, ss.y, twiddle(tw0, tw1, ka + 1024 * k1));
     }
     if (tid == 0) {
-      // task (0, 0): bins 1024 k1, partners k1 <-> 16 - k1, bins 0 and NC/2 alone;
-      // task (0, 16): bins 512 + 1024 k1, partners k1 <-> 15 - k1
-      spectrum_self(own[0], S[0], S[kNC], twiddle(tw0, tw1, 0));
-      spectrum_self(own[8], S[kNC / 2], S[kNC / 2], twiddle(tw0, tw1, kNC / 2));
-#pragma unroll 1
-      for (int k1 = 1; k1 < 8; ++k1)
-        spectrum_pair(own[k1], own[16 - k1], S[1024 * k1], S[kNC - 1024 * k1],
-                      twiddle(tw0, tw1, 1024 * k1));
-#pragma unroll 1
-      for (int k1 = 0; k1 < 8; ++k1) {
-        const int k = 512 + 1024 * k1;
-        spectrum_pair(own[16 + k1], own[31 - k1], S[k], S[kNC - k], twiddle(tw0, tw1, k));
-      }
 #pragma unroll
       for (int i = 0; i < 32; ++i) v[i] = own[i];
     }
   }
+  __syncthreads();  // the staged symbol is read: the transposes may reuse the buffer
 
   // ---- inverse: the transposed steps --------------------------------------------------------
   dft16_at<0>(v);
@@ -418,7 +457,37 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
+// Symbol pairs of every band in the register kernel's read order: entry [k1][thread] is
+// (S[k], S[NC - k]) for bin k = a3 + 32 a2 + 1024 k1 of the thread's first task; then the 8
+// bins 512 + 1024 j of the first thread's second task.
+__global__ __launch_bounds__(kT) void k_reg_table(const float* __restrict__ spec,
+                                                  float2* __restrict__ tab) {
+  const int tid = threadIdx.x;
+  const float* __restrict__ S = spec + static_cast<int64_t>(blockIdx.x) * (kNC + 1);
+  float2* __restrict__ T = tab + static_cast<int64_t>(blockIdx.x) * kTab;
+  int a3, a2, b3, b2;
+  reg_tasks(tid, a3, a2, b3, b2);
+  const int ka = a3 + 32 * a2;
+  for (int k1 = 0; k1 < 16; ++k1) {
+    const int k = ka + 1024 * k1;
+    T[k1 * kT + tid] = make_float2(S[k], S[kNC - k]);
+  }
+  if (tid < 8) {
+    const int k = 512 + 1024 * tid;
+    T[16 * kT + tid] = make_float2(S[k], S[kNC - k]);
+  }
+}
+
 }  // namespace
+
+mm_status build_reg_table(Plan* P, hipStream_t s) {
+  if (P->n_bands == 0) return MM_OK;
+  MM_TRY(dalloc(P, &P->spec_reg, static_cast<size_t>(P->n_bands) * kTab));
+  hipLaunchKernelGGL(k_reg_table, dim3(static_cast<unsigned>(P->n_bands)), dim3(kT), 0, s,
+                     P->spec, P->spec_reg);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
 
 bool apply_reg_supported(const Plan* P) {
   return P->fft_n == kN && P->fft_n - 2 * static_cast<int64_t>(P->lambda_max) <= kHalf;
@@ -426,18 +495,19 @@ bool apply_reg_supported(const Plan* P) {
 
 mm_status launch_apply_reg(Plan* P, const double* x, const float* d, int64_t ldx, double* y,
                            int64_t ldy, int32_t ncol, const int32_t* done, hipStream_t s) {
-  if (!apply_reg_supported(P)) return fail(MM_ERR_UNSUPPORTED, "register FFT kernel: segment shape");
+  if (!apply_reg_supported(P) || P->spec_reg == nullptr)
+    return fail(MM_ERR_UNSUPPORTED, "register FFT kernel: segment shape");
   const bool vec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 && (ldx & 3) == 0;
   const int d_vec = vec ? 1 : 0;
   const int64_t grid = static_cast<int64_t>(P->n_chunks) * ncol;
   if (grid > INT32_MAX) return fail(MM_ERR_UNSUPPORTED, "too many segment x column workgroups");
   if (d != nullptr) {
     hipLaunchKernelGGL((k_apply_reg<true>), dim3(static_cast<unsigned>(grid)), dim3(kT), 0, s,
-                       P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks, P->spec,
+                       P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks, P->spec_reg,
                        P->tw0, P->tw1, P->lambda_max, done);
   } else {
     hipLaunchKernelGGL((k_apply_reg<false>), dim3(static_cast<unsigned>(grid)), dim3(kT), 0, s,
-                       P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks, P->spec,
+                       P->lpix, P->wq, P->wu, x, d, d_vec, y, ncol, ldx, ldy, P->chunks, P->spec_reg,
                        P->tw0, P->tw1, P->lambda_max, done);
   }
   MM_HIP_TRY(hipGetLastError());

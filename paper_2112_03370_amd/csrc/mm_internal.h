@@ -167,6 +167,7 @@ struct Plan {
   int64_t* band_off = nullptr;
   int32_t* band_ncoef = nullptr;
   float* spec = nullptr;        // [n_bands][fft_n/2 + 1], scaled for the in-kernel transform
+  float2* spec_reg = nullptr;   // symbol pairs in the register FFT kernel's read order
   float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
   float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
@@ -244,6 +245,7 @@ mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y
                              int64_t ldx = 0, int64_t ldy = 0);
 // Register-resident variant for 2^15-sample segments with at most 2^14 outputs (apply_reg.hip).
 bool apply_reg_supported(const Plan* P);
+mm_status build_reg_table(Plan* P, hipStream_t s);  // after the band spectra
 mm_status launch_apply_reg(Plan* P, const double* x, const float* d, int64_t ldx, double* y,
                            int64_t ldy, int32_t ncol, const int32_t* done, hipStream_t s);
 mm_status launch_zero(double* y, int64_t n, hipStream_t s);

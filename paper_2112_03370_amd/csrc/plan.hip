@@ -500,7 +500,7 @@ void work_free(Work* W) {
 void destroy_plan(Plan* P) {
   if (!P) return;
   void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
-                  P->band_ncoef, P->spec, P->tw0, P->tw1, P->chunks, P->tiles, P->id_tiles,
+                  P->band_ncoef, P->spec, P->spec_reg, P->tw0, P->tw1, P->chunks, P->tiles, P->id_tiles,
                   P->id_seg};
   for (void* p : ptrs) dev_free(p);
   work_free(&P->work);
@@ -746,6 +746,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     P->fused = false;  // long segments: gather, four-step product and scatter as three kernels
   P->reg_fft = algo == MM_TOEPLITZ_FFT && P->fused && (g->flags & MM_FLAG_LDS_FFT) == 0 &&
                apply_reg_supported(P);
+  if (P->reg_fft) MM_TRY(build_reg_table(P, s));
   MM_TRY(work_alloc(P, &P->work));
   P->device_bytes += P->work.bytes;
 
