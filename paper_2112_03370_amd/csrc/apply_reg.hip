@@ -232,6 +232,42 @@ __device__ __forceinline__ void spectrum_self(float2& X, float sa, float sb, flo
   X = make_float2(p * X.x + q * X.y, -(p * X.y + q * X.x));
 }
 
+// Window samples [H kHalf, (H + 1) kHalf) (zero outside the block [b0, b1)) through LDS into
+// the A layout: z[t + 512 j] = (t[2m], t[2m+1]), m = t + 512 j, j in [16 H, 16 H + 16).
+template <int H, bool kFromData>
+__device__ __forceinline__ void gather_half(float2 (&v)[32], float* lds, int tid,
+                                            const int32_t* __restrict__ lpix,
+                                            const float* __restrict__ wq,
+                                            const float* __restrict__ wu,
+                                            const double* __restrict__ x,
+                                            const float* __restrict__ d, int d_vec, int64_t in0,
+                                            int64_t b0, int64_t b1) {
+  for (int n = tid * kLane; n < kHalf; n += kT * kLane) {
+    const int64_t g = in0 + H * kHalf + n;
+    float s[kLane];
+    if (g >= b0 && g + kLane <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
+      LanePointing<kLane, kFromData> lane;
+      lane.load(lpix, wq, wu, d, g);
+      lane.resolve(x, s);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kLane; ++j) {
+        const int64_t gj = g + j;
+        s[j] = 0.0f;
+        if (gj >= b0 && gj < b1)
+          s[j] = gather_one<kFromData>(lpix[gj], wq[gj], wu[gj], x, kFromData ? d[gj] : 0.0f);
+      }
+    }
+    *reinterpret_cast<float4*>(lds + n) = make_float4(s[0], s[1], s[2], s[3]);
+    *reinterpret_cast<float4*>(lds + n + 4) = make_float4(s[4], s[5], s[6], s[7]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj)
+    v[16 * H + jj] = *reinterpret_cast<const float2*>(lds + 2 * (tid + kT * jj));
+  __syncthreads();
+}
+
 template <bool kFromData>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_apply_reg(
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
@@ -267,33 +303,16 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   float2 v[32];
 
   // ---- gather the window in two halves of 16,384 samples through LDS ----------------------
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    for (int n = tid * kLane; n < kHalf; n += kT * kLane) {
-      const int64_t g = in0 + h * kHalf + n;
-      float s[kLane];
-      if (g >= b0 && g + kLane <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
-        LanePointing<kLane, kFromData> lane;
-        lane.load(lpix, wq, wu, d, g);
-        lane.resolve(x, s);
-      } else {
-#pragma unroll
-        for (int j = 0; j < kLane; ++j) {
-          const int64_t gj = g + j;
-          s[j] = 0.0f;
-          if (gj >= b0 && gj < b1)
-            s[j] = gather_one<kFromData>(lpix[gj], wq[gj], wu[gj], x, kFromData ? d[gj] : 0.0f);
-        }
-      }
-      *reinterpret_cast<float4*>(lds + n) = make_float4(s[0], s[1], s[2], s[3]);
-      *reinterpret_cast<float4*>(lds + n + 4) = make_float4(s[4], s[5], s[6], s[7]);
-    }
-    __syncthreads();
-    // z[t + 512 j] = (t[2m], t[2m+1]), m = t + 512 j, j in [16 h, 16 h + 16)
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj)
-      v[16 * h + jj] = *reinterpret_cast<const float2*>(lds + 2 * (tid + kT * jj));
-    __syncthreads();
+  // The right half of a segment's window is the left half of the next segment's (lambda = 2^13;
+  // nearly so otherwise), and neighbouring segments run at the same time on one XCD: even
+  // segments gather their right half first and odd ones their left half first, so that both
+  // readers of a shared half fetch it together and the second finds it in L2.
+  if (((wg / ncol) & 1) == 0) {
+    gather_half<1, kFromData>(v, lds, tid, lpix, wq, wu, x, d, d_vec, in0, b0, b1);
+    gather_half<0, kFromData>(v, lds, tid, lpix, wq, wu, x, d, d_vec, in0, b0, b1);
+  } else {
+    gather_half<0, kFromData>(v, lds, tid, lpix, wq, wu, x, d, d_vec, in0, b0, b1);
+    gather_half<1, kFromData>(v, lds, tid, lpix, wq, wu, x, d, d_vec, in0, b0, b1);
   }
 
   // ---- forward transform --------------------------------------------------------------------
