@@ -43,23 +43,44 @@ __global__ __launch_bounds__(kThreads) void k_plan_accumulate(
   const BjFlush flush{B, hits};
   const double c0 = tl.c0;
   for (int off = 0; off < tl.len; off += kThreads * 4) {
+    const int o0 = off + threadIdx.x * 4;
+    const int64_t i0 = tl.start + o0;
+    int gg[4];
+    float qq[4], uu[4];
+    bool in[4];
+    if (o0 + 4 <= tl.len && (i0 & 3) == 0) {  // one 16-byte load per stream
+      const int4 g4 = *reinterpret_cast<const int4*>(pix + i0);
+      const float4 q4 = *reinterpret_cast<const float4*>(wq + i0);
+      const float4 u4 = *reinterpret_cast<const float4*>(wu + i0);
+      gg[0] = g4.x; gg[1] = g4.y; gg[2] = g4.z; gg[3] = g4.w;
+      qq[0] = q4.x; qq[1] = q4.y; qq[2] = q4.z; qq[3] = q4.w;
+      uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) in[j] = true;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        in[j] = o0 + j < tl.len;
+        gg[j] = in[j] ? pix[i0 + j] : -1;
+        qq[j] = in[j] ? wq[i0 + j] : 0.0f;
+        uu[j] = in[j] ? wu[i0 + j] : 0.0f;
+      }
+    }
     int key[4];
     double v[4][7];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int o = off + threadIdx.x * 4 + j;
       key[j] = -1;
 #pragma unroll
       for (int c = 0; c < 7; ++c) v[j][c] = 0.0;
-      if (o < tl.len) {
-        const int64_t i = tl.start + o;
-        int g = pix[i];
+      if (in[j]) {
+        int g = gg[j];
         if (g < -1 || g >= n_pix_global) {
           atomicOr(err, 1);
           g = -1;
         }
         key[j] = g;
-        const double q = wq[i], u = wu[i];
+        const double q = qq[j], u = uu[j];
         v[j][0] = c0;
         v[j][1] = c0 * q;
         v[j][2] = c0 * u;
@@ -246,8 +267,9 @@ __global__ __launch_bounds__(kThreads) void k_plan_remap(const int32_t* __restri
 // ---- band symbols f(w) = c_0 + 2 sum_k c_k cos(k w) on an M-point grid (Clenshaw, FP64) -----
 // Each thread runs kSymPts independent recurrences (grid points k, k + S, k + 2S, ... with S the
 // number of threads of the band) that share every coefficient load: one chain alone would wait
-// on its own FMA latency at every step.
-constexpr int kSymPts = 4;
+// on its own FMA latency at every step.  A step is b_j = 2x b_{j+1} + (2c_j - b_{j+2}): the
+// bracket is known a step early, so each chain's critical path is one FMA per coefficient.
+constexpr int kSymPts = 8;
 
 __global__ __launch_bounds__(kThreads) void k_band_symbol(
     const float* __restrict__ coef, const int64_t* __restrict__ off,
@@ -259,11 +281,12 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
   const float* cs = coef + off[band];  // every lane reads the same coefficient: broadcast loads
   const int stride = gridDim.x * kThreads;
   int k[kSymPts];
-  double x[kSymPts], b1[kSymPts], b2[kSymPts];
+  double x[kSymPts], x2[kSymPts], b1[kSymPts], b2[kSymPts];
 #pragma unroll
   for (int p = 0; p < kSymPts; ++p) {
     k[p] = blockIdx.x * kThreads + threadIdx.x + p * stride;
     x[p] = cospi(2.0 * static_cast<double>(k[p]) / static_cast<double>(M));
+    x2[p] = 2.0 * x[p];
     b1[p] = 0.0;
     b2[p] = 0.0;
   }
@@ -278,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
     for (int q = 0; q < 8; ++q) {
 #pragma unroll
       for (int p = 0; p < kSymPts; ++p) {
-        const double b0 = c2[q] + 2.0 * x[p] * b1[p] - b2[p];
+        const double b0 = fma(x2[p], b1[p], c2[q] - b2[p]);  // b2 is known a step early
         b2[p] = b1[p];
         b1[p] = b0;
       }
@@ -288,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
     const double c2 = 2.0 * static_cast<double>(cs[j]);
 #pragma unroll
     for (int p = 0; p < kSymPts; ++p) {
-      const double b0 = c2 + 2.0 * x[p] * b1[p] - b2[p];
+      const double b0 = fma(x2[p], b1[p], c2 - b2[p]);
       b2[p] = b1[p];
       b1[p] = b0;
     }
