@@ -61,8 +61,16 @@ __global__ __launch_bounds__(FftCfg<LOG>::T) void k_apply_fused(
   const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
 
   // ---- gather the N-sample window (zero outside the block) ---------------------------------
+  // Four rounds of T SG samples, one window quarter each.  With N = 4 lambda the right half of
+  // the window is the left half of the next segment's, and neighbouring segments run at the
+  // same time on one XCD: even segments gather their right half first, odd ones their left
+  // half first, so both readers of a shared half fetch it together and the second finds it in
+  // L2.
   constexpr int SG = kGatherLane;
-  for (int n = tid * SG; n < N; n += T * SG) {
+  static_assert(N == 4 * T * SG, "four gather rounds");
+  const int rot = ((wg / ncol) & 1) == 0 ? 2 : 0;
+  for (int rr = 0; rr < 4; ++rr) {
+    const int n = ((rr + rot) & 3) * (T * SG) + tid * SG;
     const int64_t g = in0 + n;
     float v[SG];
     if (g >= b0 && g + SG <= b1 && (g & 3) == 0 && (!kFromData || d_vec)) {
