@@ -342,6 +342,100 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
   }
 }
 
+// The same symbol on large grids (M >= 4096) in two levels, with j = p + 64 q and the grid
+// point k = r + (M/64) s:
+//   f(2 pi k / M) = Re sum_p e^{2 pi i p k / M} G_p(r),   G_p(r) = sum_q w_{p+64q} e^{2 pi i q r / (M/64)}
+// (w_0 = c_0, w_j = 2 c_j): the inner sums depend on k only through r, so each is formed once for
+// the 64 values of s that share it, about a tenth of the Clenshaw work at lambda = M/8.  A
+// workgroup takes 16 consecutive r for one band: phase 1 builds its 64 x 16 inner sums in LDS
+// (powers of e^{2 pi i r/(M/64)} by multiplication, re-anchored every 32 steps), phase 2 the grid
+// points k <= M/2 with those r.  All FP64.
+constexpr int kSymP = 64;   // inner stride
+constexpr int kSymR = 16;   // r values per workgroup
+
+__global__ __launch_bounds__(kThreads) void k_band_symbol2(
+    const float* __restrict__ coef, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ ncoef, int M, int fft_n, float* __restrict__ spec,
+    double* __restrict__ block_min) {
+  static_assert(kThreads == 256 && kSymP * kSymR == 4 * kThreads, "thread mapping");
+  __shared__ double gr[kSymP * kSymR], gi[kSymP * kSymR];
+  __shared__ double red[kThreads / 64];
+  const int band = blockIdx.y;
+  const int nc = ncoef[band];
+  const float* cs = coef + off[band];
+  const int MP = M / kSymP;
+  const int r0 = blockIdx.x * kSymR;
+  const int tid = threadIdx.x;
+  // ---- phase 1: inner sums G_p(r) for p = 4 g .. 4 g + 3 and r = r0 + rr ---------------------
+  {
+    const int rr = tid & (kSymR - 1), g = tid >> 4;
+    const int r = r0 + rr;
+    double zs, zc;
+    sincospi(2.0 * static_cast<double>(r) / static_cast<double>(MP), &zs, &zc);
+    double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+    double qr = 1.0, qi = 0.0;
+    const int Q = (nc + kSymP - 1) / kSymP;
+    for (int q = 0; q < Q; ++q) {
+      if ((q & 31) == 0 && q > 0) {  // re-anchor z^q
+        const int64_t e = (static_cast<int64_t>(q) * r) % MP;
+        sincospi(2.0 * static_cast<double>(e) / static_cast<double>(MP), &qi, &qr);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = 4 * g + i + kSymP * q;
+        const double w = j >= nc ? 0.0 : (j == 0 ? 1.0 : 2.0) * static_cast<double>(cs[j]);
+        ar[i] = fma(w, qr, ar[i]);
+        ai[i] = fma(w, qi, ai[i]);
+      }
+      const double nr = qr * zc - qi * zs, ni = qr * zs + qi * zc;
+      qr = nr;
+      qi = ni;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      gr[(4 * g + i) * kSymR + rr] = ar[i];
+      gi[(4 * g + i) * kSymR + rr] = ai[i];
+    }
+  }
+  __syncthreads();
+  // ---- phase 2: grid points k = r0 + rr + MP s <= M/2 ----------------------------------------
+  double m = INFINITY;
+  for (int pt = tid; pt < kSymR * (kSymP / 2 + 1); pt += kThreads) {
+    const int rr = pt & (kSymR - 1), sidx = pt >> 4;
+    const int k = r0 + rr + MP * sidx;
+    if (k > M / 2) continue;
+    double us, uc;
+    sincospi(2.0 * static_cast<double>(k) / static_cast<double>(M), &us, &uc);
+    double vr = 1.0, vi = 0.0, f = 0.0;
+    for (int p = 0; p < kSymP; ++p) {
+      if ((p & 15) == 0 && p > 0) {  // re-anchor u^p
+        const int64_t e = (static_cast<int64_t>(p) * k) % M;
+        sincospi(2.0 * static_cast<double>(e) / static_cast<double>(M), &vi, &vr);
+      }
+      f = fma(vr, gr[p * kSymR + rr], f);
+      f = fma(-vi, gi[p * kSymR + rr], f);
+      const double nr = vr * uc - vi * us, ni = vr * us + vi * uc;
+      vr = nr;
+      vi = ni;
+    }
+    m = fmin(m, f);
+    if (spec != nullptr) {
+      const int step = M / fft_n;
+      if (k % step == 0)
+        spec[static_cast<int64_t>(band) * (fft_n / 2 + 1) + k / step] =
+            static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_down(m, o));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double rm = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) rm = fmin(rm, red[w]);
+    block_min[static_cast<int64_t>(band) * gridDim.x + blockIdx.x] = rm;
+  }
+}
+
 // Stream-ordered upload (no legacy-stream operation: other threads may be capturing graphs on
 // their own streams meanwhile); synchronous, since h is released by the caller afterwards.
 template <class T>
@@ -728,11 +822,17 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     while (M < 8 * lambda_max) M *= 2;
     if (fft_n > M) M = fft_n;
     if (algo == MM_TOEPLITZ_FFT) MM_TRY(dalloc(P, &P->spec, static_cast<size_t>(g->n_bands) * (fft_n / 2 + 1)));
-    const int gx = (M / 2 + 1 + kThreads * kSymPts - 1) / (kThreads * kSymPts);
+    const bool two_level = M >= 4096;  // Clenshaw below: small grids are cheap either way
+    const int gx = two_level ? M / (kSymP * kSymR)
+                             : (M / 2 + 1 + kThreads * kSymPts - 1) / (kThreads * kSymPts);
     Scratch<double> mins;
     MM_TRY(mins.alloc(static_cast<size_t>(gx) * g->n_bands));
-    hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
-                       P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
+    if (two_level)
+      hipLaunchKernelGGL(k_band_symbol2, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
+                         P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
+    else
+      hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
+                         P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
     MM_HIP_TRY(hipGetLastError());
     std::vector<double> h_mins(static_cast<size_t>(gx) * g->n_bands);
     MM_HIP_TRY(hipMemcpyAsync(h_mins.data(), mins.p, h_mins.size() * sizeof(double),
