@@ -168,6 +168,7 @@ struct Plan {
   int32_t* band_ncoef = nullptr;
   float* spec = nullptr;        // [n_bands][fft_n/2 + 1], scaled for the in-kernel transform
   float2* spec_reg = nullptr;   // symbol pairs in the register FFT kernel's read order
+  float2* long_pq = nullptr;    // spectrum-step coefficients in the long kernel's read order
   float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
   float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
@@ -298,5 +299,6 @@ bool long_fft_size(int32_t n);
 int32_t long_fine_size();
 mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, float2* scratch,
                                const int32_t* done, hipStream_t s);
+mm_status build_long_table(Plan* P, hipStream_t s);  // after the band spectra
 
 }  // namespace mm

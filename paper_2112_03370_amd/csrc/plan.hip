@@ -616,9 +616,10 @@ void work_free(Work* W) {
 
 void destroy_plan(Plan* P) {
   if (!P) return;
-  void* ptrs[] = {P->lpix, P->wq, P->wu, P->minv, P->hits, P->kept_ids, P->band_coef, P->band_off,
-                  P->band_ncoef, P->spec, P->spec_reg, P->tw0, P->tw1, P->chunks, P->tiles, P->id_tiles,
-                  P->id_seg};
+  void* ptrs[] = {P->lpix,       P->wq,       P->wu,      P->minv,     P->hits,
+                  P->kept_ids,   P->band_coef, P->band_off, P->band_ncoef, P->spec,
+                  P->spec_reg,   P->long_pq,  P->tw0,     P->tw1,      P->chunks,
+                  P->tiles,      P->id_tiles, P->id_seg};
   for (void* p : ptrs) dev_free(p);
   work_free(&P->work);
   deflation_free(&P->defl);
@@ -870,6 +871,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   P->reg_fft = algo == MM_TOEPLITZ_FFT && P->fused && (g->flags & MM_FLAG_LDS_FFT) == 0 &&
                apply_reg_supported(P);
   if (P->reg_fft) MM_TRY(build_reg_table(P, s));
+  if (algo == MM_TOEPLITZ_FFT) MM_TRY(build_long_table(P, s));
   MM_TRY(work_alloc(P, &P->work));
   P->device_bytes += P->work.bytes;
 

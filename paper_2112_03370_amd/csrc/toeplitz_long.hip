@@ -8,7 +8,10 @@
 //   F2  16 rows at a time, grouped as (k1, N1 - k1) pairs: DFT over n2 gives X[k1 + N1 k2];
 //       with both rows of every pair in LDS, unpack the real spectrum, multiply by the band
 //       symbol and repack (conjugated) in place; the inverse's first DFT (over k2) and its
-//       twiddle exp(-2 pi i k1 m2 / NC) follow in LDS; store back to the same rows
+//       twiddle exp(-2 pi i k1 m2 / NC) follow in LDS; store back to the same rows.  The
+//       spectrum step is Z'[k] = p_k conj(Z[k]) - i q_k Z[NC - k] with two real coefficients
+//       per bin (derivation with symbol_multiply); the plan stores (p_k, q_k) in exactly the
+//       order F2 visits the bins, so that each lane reads them with one coalesced load.
 //   F3  16 columns at a time: DFT over k1 yields the inverse in natural order; write the
 //       segment's outputs (real parts at even samples, minus imaginary parts at odd ones)
 //
@@ -97,10 +100,31 @@ __device__ __forceinline__ int row_of(int g, int r) {
   return (r & 1) ? N1 - k : k;
 }
 
+// (p_k, q_k) for the bins of F2 in visiting order: entry (g 16 + r) 256 + k2 is bin
+// k = row_of(g, r) + N1 k2, with p_k = 2 (sigma - delta sin(2 pi k / N)),
+// q_k = 2 delta cos(2 pi k / N), sigma and delta the sum and difference of the symbol at k and
+// NC - k.  FP64, rounded once.
+template <int LOGNC>
+__global__ __launch_bounds__(kLongThreads) void k_long_table(const float* __restrict__ spec,
+                                                             float2* __restrict__ tab) {
+  constexpr int NC = 1 << LOGNC, N1 = NC / kN2;
+  const int e = blockIdx.x * kLongThreads + threadIdx.x;  // < NC
+  const int band = blockIdx.y;
+  const int g = e / (kGroup * kN2), r = (e / kN2) % kGroup, k2 = e % kN2;
+  const int k = row_of<N1>(g, r) + N1 * k2;
+  const float* S = spec + static_cast<int64_t>(band) * (NC + 1);
+  const double sa = S[k], sb = S[NC - k];
+  const double sig = 2.0 * (sa + sb), del = 2.0 * (sa - sb);
+  double sn, cs;
+  sincospi(static_cast<double>(k) / static_cast<double>(NC), &sn, &cs);  // angle 2 pi k / N
+  tab[static_cast<int64_t>(band) * NC + e] =
+      make_float2(static_cast<float>(sig - del * sn), static_cast<float>(del * cs));
+}
+
 template <int LOGNC>
 __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
     const float* __restrict__ t, float* __restrict__ u, const Chunk* __restrict__ chunks,
-    const float* __restrict__ spec, const float2* __restrict__ tw0g,
+    const float2* __restrict__ pqtab, const float2* __restrict__ tw0g,
     const float2* __restrict__ tw1g, float2* __restrict__ scratch, int lam,
     const int32_t* __restrict__ done) {
   constexpr int NC = 1 << LOGNC, NN = 2 * NC, N1 = NC / kN2;
@@ -141,7 +165,7 @@ __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
   }
 
   // ---- F2: row DFTs, symbol, inverse row DFTs ----------------------------------------------
-  const float* S = spec + static_cast<int64_t>(c.band) * (NC + 1);
+  const float2* __restrict__ PQ = pqtab + static_cast<int64_t>(c.band) * NC;
   for (int g = 0; g < N1 / kGroup; ++g) {
     for (int idx = tid; idx < GL; idx += kLongThreads) {
       const int r = idx >> 8, n2 = idx & 255;
@@ -160,16 +184,8 @@ __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
       const int rp = (k1 == 0 || k1 == N1 / 2) ? r : (r ^ 1);
       const float2 Zk = buf[pad(idx)];
       const float2 Z2 = buf[pad(rp * kN2 + kk / N1)];
-      const float2 E = make_float2(Zk.x + Z2.x, Zk.y - Z2.y);
-      const float2 O = make_float2(Zk.y + Z2.y, Z2.x - Zk.x);
-      const float2 W = tw(k);
-      const float2 WO = cmul(W, O);
-      const float sa = S[k], sb = S[NC - k];
-      const float2 Ya = make_float2(sa * (E.x + WO.x), sa * (E.y + WO.y));
-      const float2 Yb = make_float2(sb * (E.x - WO.x), sb * (E.y - WO.y));
-      const float2 Ye = cadd(Ya, Yb);
-      const float2 Yo = cmulc(csub(Ya, Yb), W);
-      w[i] = make_float2(Ye.x - Yo.y, -(Ye.y + Yo.x));  // conj(Ye + i Yo)
+      const float2 pq = PQ[g * GL + idx];
+      w[i] = make_float2(pq.x * Zk.x + pq.y * Z2.y, -(pq.x * Zk.y + pq.y * Z2.x));
     }
     __syncthreads();
 #pragma unroll
@@ -208,18 +224,32 @@ __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
 
 bool long_fft_size(int32_t n) { return n == (1 << 16) || n == (1 << 17); }
 
+mm_status build_long_table(Plan* P, hipStream_t s) {
+  if (P->n_bands == 0 || !long_fft_size(P->fft_n)) return MM_OK;
+  const int NC = P->fft_n / 2;
+  MM_TRY(dalloc(P, &P->long_pq, static_cast<size_t>(P->n_bands) * NC));
+  const dim3 grid(static_cast<unsigned>(NC / kLongThreads), static_cast<unsigned>(P->n_bands));
+  if (P->fft_n == (1 << 16))
+    hipLaunchKernelGGL(k_long_table<15>, grid, dim3(kLongThreads), 0, s, P->spec, P->long_pq);
+  else
+    hipLaunchKernelGGL(k_long_table<16>, grid, dim3(kLongThreads), 0, s, P->spec, P->long_pq);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
 int32_t long_fine_size() { return kFine; }
 
 mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, float2* scratch,
                                const int32_t* done, hipStream_t s) {
   if (P->n_chunks == 0) return MM_OK;
   if (scratch == nullptr) return fail(MM_ERR_INVALID, "long-segment product without its tiles");
+  if (P->long_pq == nullptr) return fail(MM_ERR_INVALID, "long-segment product without its table");
   if (P->fft_n == (1 << 16)) {
     hipLaunchKernelGGL(k_toeplitz_long<15>, dim3(P->n_chunks), dim3(kLongThreads), 0, s, t, u,
-                       P->chunks, P->spec, P->tw0, P->tw1, scratch, P->lambda_max, done);
+                       P->chunks, P->long_pq, P->tw0, P->tw1, scratch, P->lambda_max, done);
   } else if (P->fft_n == (1 << 17)) {
     hipLaunchKernelGGL(k_toeplitz_long<16>, dim3(P->n_chunks), dim3(kLongThreads), 0, s, t, u,
-                       P->chunks, P->spec, P->tw0, P->tw1, scratch, P->lambda_max, done);
+                       P->chunks, P->long_pq, P->tw0, P->tw1, scratch, P->lambda_max, done);
   } else {
     return fail(MM_ERR_UNSUPPORTED, "long FFT size not supported");
   }
