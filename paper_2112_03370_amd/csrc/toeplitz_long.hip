@@ -125,8 +125,9 @@ template <int LOGNC>
 __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
     const float* __restrict__ t, float* __restrict__ u, const Chunk* __restrict__ chunks,
     const float2* __restrict__ pqtab, const float2* __restrict__ tw0g,
-    const float2* __restrict__ tw1g, float2* __restrict__ scratch, int lam,
+    const float2* __restrict__ tw1g, float2* __restrict__ scratch, int lam, int vec8,
     const int32_t* __restrict__ done) {
+  // vec8: t and u are 8-byte aligned, so even sample indices allow 8-byte accesses
   constexpr int NC = 1 << LOGNC, NN = 2 * NC, N1 = NC / kN2;
   constexpr int GL = kGroup * kN2;
   static_assert(N1 == 128 || N1 == 256, "tile shape");
@@ -151,9 +152,14 @@ __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
     for (int idx = tid; idx < kGroup * N1; idx += kLongThreads) {
       const int n1 = idx >> 4, cc = idx & 15;
       const int64_t gs = in0 + 2 * (static_cast<int64_t>(n1) * kN2 + kGroup * g + cc);
-      const float a = (gs >= b0 && gs < b1) ? t[gs] : 0.0f;
-      const float b = (gs + 1 >= b0 && gs + 1 < b1) ? t[gs + 1] : 0.0f;
-      buf[pad(cc * N1 + n1)] = make_float2(a, b);
+      float2 ab;
+      if (vec8 && gs >= b0 && gs + 1 < b1 && (gs & 1) == 0) {  // one 8-byte load
+        ab = *reinterpret_cast<const float2*>(t + gs);
+      } else {
+        ab.x = (gs >= b0 && gs < b1) ? t[gs] : 0.0f;
+        ab.y = (gs + 1 >= b0 && gs + 1 < b1) ? t[gs + 1] : 0.0f;
+      }
+      buf[pad(cc * N1 + n1)] = ab;
     }
     __syncthreads();
     batched_fft<N1, kGroup, NN>(buf, tw);
@@ -213,8 +219,12 @@ __global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
       const int m = m1 * kN2 + kGroup * g + cc;
       const float2 F = buf[pad(cc * N1 + m1)];
       const int o = 2 * m - lam;  // segment output offset of the real sample 2m
-      if (o >= 0 && o < c.out_len) u[c.out0 + o] = F.x;
-      if (o + 1 >= 0 && o + 1 < c.out_len) u[c.out0 + o + 1] = -F.y;
+      if (vec8 && o >= 0 && o + 1 < c.out_len && ((c.out0 + o) & 1) == 0) {  // one 8-byte store
+        *reinterpret_cast<float2*>(u + c.out0 + o) = make_float2(F.x, -F.y);
+      } else {
+        if (o >= 0 && o < c.out_len) u[c.out0 + o] = F.x;
+        if (o + 1 >= 0 && o + 1 < c.out_len) u[c.out0 + o + 1] = -F.y;
+      }
     }
     __syncthreads();
   }
@@ -244,12 +254,13 @@ mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, float2* scratc
   if (P->n_chunks == 0) return MM_OK;
   if (scratch == nullptr) return fail(MM_ERR_INVALID, "long-segment product without its tiles");
   if (P->long_pq == nullptr) return fail(MM_ERR_INVALID, "long-segment product without its table");
+  const int vec8 = ((reinterpret_cast<uintptr_t>(t) | reinterpret_cast<uintptr_t>(u)) & 7u) == 0;
   if (P->fft_n == (1 << 16)) {
     hipLaunchKernelGGL(k_toeplitz_long<15>, dim3(P->n_chunks), dim3(kLongThreads), 0, s, t, u,
-                       P->chunks, P->long_pq, P->tw0, P->tw1, scratch, P->lambda_max, done);
+                       P->chunks, P->long_pq, P->tw0, P->tw1, scratch, P->lambda_max, vec8, done);
   } else if (P->fft_n == (1 << 17)) {
     hipLaunchKernelGGL(k_toeplitz_long<16>, dim3(P->n_chunks), dim3(kLongThreads), 0, s, t, u,
-                       P->chunks, P->long_pq, P->tw0, P->tw1, scratch, P->lambda_max, done);
+                       P->chunks, P->long_pq, P->tw0, P->tw1, scratch, P->lambda_max, vec8, done);
   } else {
     return fail(MM_ERR_UNSUPPORTED, "long FFT size not supported");
   }

@@ -299,6 +299,23 @@ def test_invalid_inputs_are_rejected(gpu_lib):
 # Long bands: four-step segments of 2^16 and 2^17 samples
 # ------------------------------------------------------------------------------------------
 
+def test_noise_weight_long_band_unaligned_buffers(gpu_lib):
+    # caller buffers at a 4-byte offset: the long kernel must take its scalar loads and stores
+    import torch
+    prob = synth.make_ground(cfg_id=26, n_dets=1, samples_per_det=200000, interval=200000,
+                             side=16, lam=20000)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT)
+    assert plan.info["fft_size"] == 131072
+    n = prob.n_samples
+    t = np.random.default_rng(10).standard_normal(n).astype(np.float32)
+    want = plan.noise_weight(_dev(t)).cpu().numpy()
+    tb = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    ub = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    tb[1:] = _dev(t)
+    got = plan.noise_weight(tb[1:], ub[1:]).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("lam,fft_size", [(12001, 65536), (20000, 131072), (32768, 0)])
 def test_noise_weight_long_band(gpu_lib, lam, fft_size):
     prob = synth.make_ground(cfg_id=25, n_dets=2, samples_per_det=300001, interval=200003,
