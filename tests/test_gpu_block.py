@@ -36,6 +36,10 @@ CASES = {
     "ground_rhs4": lambda: synth.make_ground(cfg_id=62, n_dets=6, samples_per_det=40000,
                                              interval=9000, side=32, lam=700, flag_frac=0.02,
                                              n_rhs=4),
+    # lambda = 8192: 2^15-sample segments through the register-resident kernel, several columns
+    "ground_lam8192_rhs3": lambda: synth.make_ground(cfg_id=65, n_dets=3, samples_per_det=70001,
+                                                     interval=35001, side=24, lam=8192,
+                                                     flag_frac=0.01, n_rhs=3),
 }
 
 _cache = {}
@@ -53,6 +57,8 @@ def case(name):
 def test_apply_A_multi_column_parity(gpu_lib, name, unfused):
     prob, ref = case(name)
     plan = gpu_lib.Plan.from_problem(prob, flags=gpu_lib.FLAG_UNFUSED if unfused else 0)
+    if name == "ground_lam8192_rhs3":
+        assert plan.info["fused"] == (0 if unfused else 2), plan.info
     X = np.random.default_rng(7).standard_normal((5, ref.n_kept, 3))
     Y = plan.apply_A(_dev(X)).cpu().numpy()
     for j in range(5):
