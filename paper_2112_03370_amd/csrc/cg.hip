@@ -381,10 +381,11 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
                      max_iter);
   MM_HIP_TRY(hipGetLastError());
 
-  // Iterate in chunks; the host reads the state between chunks.
-  // With per-kernel timing on, check after every iteration so that no launch is queued past
-  // convergence (every timed launch then does real work).
-  int chunk = P->timing.enabled ? 1 : (opts.check_every > 0 ? opts.check_every : 4);
+  // Iterate in chunks; the host reads the state between chunks.  Launches queued past
+  // convergence exit at once; with per-kernel timing on they carry their iteration number and
+  // are dropped from the timings afterwards, and the launches are eager (events per launch)
+  // instead of graph replays.
+  int chunk = opts.check_every > 0 ? opts.check_every : 4;
   const bool use_graph = opts.use_graph && !P->timing.enabled;
   hipGraphExec_t gexec = nullptr;
   int graph_chunk = 0;
@@ -442,7 +443,7 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
       if (P->timing.enabled) P->timing.tag = 0;
     }
     queued += chunk;
-    if (opts.check_every <= 0 && !P->timing.enabled && chunk < 16) chunk *= 2;
+    if (opts.check_every <= 0 && chunk < 16) chunk *= 2;
   }
 
   // True residual with one more product.

@@ -88,3 +88,21 @@ def test_lds_flag_keeps_other_shapes(gpu_lib):
                              lam=5000)
     plan = gpu_lib.Plan.from_problem(prob)
     assert plan.info["fft_size"] == 32768 and plan.info["fused"] == 1, plan.info
+
+
+def test_kernel_timing_counts_working_launches(gpu_lib):
+    # with per-kernel timing on, launches queued past convergence are dropped from the counts:
+    # one fused product for b, one per iteration, one for the true residual
+    prob, ref, pkw = case("lam8192")
+    plan = gpu_lib.Plan.from_problem(prob, **pkw)
+    d = _dev(prob.d[0])
+    x0, info0 = plan.pcg_solve(d, tol=1e-8)
+    plan.set_timing(True)
+    x1, info1 = plan.pcg_solve(d, tol=1e-8)
+    ms, n = plan.kernel_time(1)
+    plan.set_timing(False)
+    assert info1["iterations"] == info0["iterations"]
+    assert n == info1["iterations"] + 2, (n, info1["iterations"])
+    assert ms > 0.0
+    # the scatter's FP64 atomics commit in a different order on every run
+    assert float(_rel(x1.cpu().numpy(), x0.cpu().numpy())) <= 1e-8
