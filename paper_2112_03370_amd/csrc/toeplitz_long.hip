@@ -121,8 +121,12 @@ __global__ __launch_bounds__(kLongThreads) void k_long_table(const float* __rest
       make_float2(static_cast<float>(sig - del * sn), static_cast<float>(del * cs));
 }
 
+// Four waves per SIMD (four workgroups per CU, 128 registers) for N = 2^17, where that costs a
+// handful of spilled registers and hides more of each group's memory wait; N = 2^16 spills too
+// much at that limit and keeps the compiler's choice.
 template <int LOGNC>
-__global__ __launch_bounds__(kLongThreads) void k_toeplitz_long(
+__global__ __launch_bounds__(kLongThreads)
+__attribute__((amdgpu_waves_per_eu(LOGNC == 16 ? 4 : 1))) void k_toeplitz_long(
     const float* __restrict__ t, float* __restrict__ u, const Chunk* __restrict__ chunks,
     const float2* __restrict__ pqtab, const float2* __restrict__ tw0g,
     const float2* __restrict__ tw1g, float2* __restrict__ scratch, int lam, int vec8,
