@@ -288,7 +288,16 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 int64_t plan_estimate(const mm_geometry* g) {
   // pointing copies and per-sample plan data, pixel-domain vectors, a workspace
   int64_t b = 16 * g->n_samples + 120 * g->n_pix_global;
-  for (int i = 0; i < g->n_bands; ++i) b += 4 * 65538;  // band spectrum upper bound (2^17 / 2 + 1)
+  int32_t lambda_max = 0;
+  for (int i = 0; i < g->n_bands; ++i) {
+    b += 4 * 65538;  // band spectrum upper bound (2^17 / 2 + 1)
+    if (g->band_ncoef) lambda_max = std::max(lambda_max, g->band_ncoef[i] - 1);
+  }
+  // unfused products (flag, direct product, or segments beyond 2^15): FP32 time-domain work
+  // vectors of the plan's workspace
+  const bool unfused = (g->flags & MM_FLAG_UNFUSED) != 0 || g->toeplitz_algo == MM_TOEPLITZ_DIRECT ||
+                       lambda_max > 12288;
+  if (unfused && lambda_max > 0) b += 8 * g->n_samples;
   return b;
 }
 
