@@ -82,6 +82,25 @@ def test_register_kernel_pcg_map(gpu_lib):
     assert abs(info["iterations"] - want.iterations) <= 3, (info["iterations"], want.iterations)
 
 
+def test_register_kernel_mixed_band_lengths(gpu_lib):
+    # the segments use the plan's longest band as halo; a detector with a short band keeps its
+    # own symbol in the table
+    prob = synth.make_ground(cfg_id=45, n_dets=3, samples_per_det=80001, interval=40001, side=24,
+                             lam=8192, flag_frac=0.01)
+    k = np.arange(51, dtype=np.float64)
+    tail = -0.3 * np.exp(-k[1:] / 6.0)
+    short = np.concatenate([[1.0 + 2.0 * np.abs(tail).sum() + 0.2], tail]).astype(np.float32)
+    prob.bands[1] = short
+    ref = O.plan_from_problem(prob)
+    plan = gpu_lib.Plan.from_problem(prob)
+    assert plan.info["fused"] == 2 and plan.info["lambda_max"] == 8192, plan.info
+    x = np.random.default_rng(14).standard_normal((ref.n_kept, 3))
+    err = float(_rel(plan.apply_A(_dev(x)).cpu().numpy(), O.apply_A(ref, x)))
+    assert err <= 3e-6, err
+    err = float(_rel(plan.rhs(_dev(prob.d[0])).cpu().numpy(), O.rhs(ref, prob.d[0])))
+    assert err <= 3e-6, err
+
+
 def test_lds_flag_keeps_other_shapes(gpu_lib):
     # lambda < 2^13 at length 2^15 has more than 2^14 outputs per segment: LDS kernel
     prob = synth.make_ground(cfg_id=44, n_dets=2, samples_per_det=70001, interval=40001, side=24,
