@@ -7,6 +7,8 @@ kernels within that bound of each other, and the PCG map within 1e-6 of the orac
 Cases: lambda 8192 with the automatic 2^15 length, odd lambda 8193 with the length forced
 (odd output offset, 16,382 outputs per segment), lambda 12000 (8,768 outputs), odd block
 lengths (ragged last segments), flagged samples (zero rows of P), and two columns at once.
+Also blocks of exactly four segments back to back (a window's halo must not reach into the
+neighbouring block) and 13-segment blocks.
 """
 
 import numpy as np
@@ -37,6 +39,12 @@ CASES = {
                             lam=8193, flag_frac=0.01), dict(fft_size=32768)),
     "lam12000": (dict(cfg_id=43, n_dets=2, samples_per_det=90007, interval=45001, side=32,
                       lam=12000, flag_frac=0.0), {}),
+    # blocks of exactly four segments, back to back: halos stop at each block edge
+    "lam8192_exact_blocks": (dict(cfg_id=46, n_dets=2, samples_per_det=196608, interval=65536,
+                                  side=40, lam=8192, flag_frac=0.01), {}),
+    # 13 segments per block, the last one ragged
+    "lam8192_long_blocks": (dict(cfg_id=47, n_dets=2, samples_per_det=200003, interval=200003,
+                                 side=40, lam=8192, flag_frac=0.01), {}),
 }
 
 _cache = {}
