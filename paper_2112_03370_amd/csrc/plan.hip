@@ -699,10 +699,25 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   }
   if (cursor < n) add_identity(cursor, n - cursor);
 
+  // Segment order: with detector offsets, blocks run by time within their detector first and
+  // detector second, so that the segments resident together come from many detectors observing
+  // at the same moment (the same patch of sky) and share pixels in L2; the segments of one block
+  // stay consecutive (their windows overlap).
+  std::vector<int> seg_order(order);
+  if (g->det_offset != nullptr && g->n_dets > 0) {
+    auto key = [g](int b) {
+      const int64_t s0 = g->blk_start[b];
+      const int64_t* it = std::upper_bound(g->det_offset, g->det_offset + g->n_dets + 1, s0);
+      const int64_t d = (it - g->det_offset) - 1;
+      return std::make_pair(s0 - g->det_offset[d], d);
+    };
+    std::stable_sort(seg_order.begin(), seg_order.end(),
+                     [&](int a, int b) { return key(a) < key(b); });
+  }
   std::vector<Chunk> chunks;
   if (algo == MM_TOEPLITZ_FFT) {
     const int64_t L = fft_n - 2 * lambda_max;
-    for (int i : order) {
+    for (int i : seg_order) {
       const int64_t s0 = g->blk_start[i], len = g->blk_len[i];
       for (int64_t o = 0; o < len; o += L)
         chunks.push_back(Chunk{s0 + o, s0, static_cast<int32_t>(len),
@@ -710,7 +725,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
                                g->blk_band[i], 0});
     }
   } else {
-    for (int i : order) {
+    for (int i : seg_order) {
       const int64_t s0 = g->blk_start[i], len = g->blk_len[i];
       for (int64_t o = 0; o < len; o += 1024)
         chunks.push_back(Chunk{s0 + o, s0, static_cast<int32_t>(len),
