@@ -22,6 +22,7 @@ constexpr int kPerThread = 4;              // diagonal kernel
 constexpr int kPerBlock = kThreads * kPerThread;
 constexpr int kLane = 8;                   // un-pointing and pointing
 constexpr int kLaneBlock = kThreads * kLane;
+constexpr int kListed = 128;                // listed runs per wavefront in the scatter
 
 inline int grid_for(int64_t n, int per_block = kPerBlock) {
   int64_t g = (n + per_block - 1) / per_block;
@@ -152,6 +153,10 @@ __global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ done) {
   if (done != nullptr && *done) return;
   const PointFlush flush{y};
+  // per wavefront: the runs it completes, listed before the atomics
+  __shared__ int skey[kThreads / 64][kListed];
+  __shared__ double sval[kThreads / 64][3 * kListed];
+  const int wave = static_cast<int>(threadIdx.x >> 6);
   // Every lane of the block runs the same number of iterations (wavefront-collective scan).
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * kLaneBlock; base < n;
        base += static_cast<int64_t>(gridDim.x) * kLaneBlock) {
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ 
         }
       }
     }
-    wave_merge_runs_n<kLane, 3>(key, v, flush);
+    wave_merge_runs_listed<kLane, 3, kListed>(key, v, flush, skey[wave], sval[wave]);
   }
 }
 

@@ -95,6 +95,158 @@ __device__ __forceinline__ void wave_merge_runs_n(const int (&key)[SPL], const d
   }
 }
 
+// Exclusive prefix sum over the wavefront of a small per-lane count c < 2^BITS.
+template <int BITS>
+__device__ __forceinline__ int wave_exclusive_count(int c, int lane, int& total) {
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int before = 0;
+  total = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const unsigned long long m = __ballot((c >> b) & 1);
+    before += __popcll(m & below) << b;
+    total += __popcll(m) << b;
+  }
+  return before;
+}
+
+// The same merge, but the runs that the wavefront completes are first listed in LDS (CAP slots
+// of one key and NV values per wavefront, `skey` and `sval`) and then flushed one run per lane:
+// ceil(R / 64) rounds of NV atomics for R runs.  The direct form above issues one round at every
+// lane position where some lane closes a run inside it, which on scans with short runs (a
+// circle clipping pixel corners) means several rounds of nearly idle atomic instructions per
+// wavefront.  Runs beyond CAP are flushed directly.
+template <int SPL, int NV, int CAP, class Flush>
+__device__ __forceinline__ void wave_merge_runs_listed(const int (&key)[SPL],
+                                                       const double (&v)[SPL][NV],
+                                                       const Flush& flush, int* skey,
+                                                       double* sval) {
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+
+  // ---- runs inside the lane: count, then list ---------------------------------------------
+  // A run starting at a key change j > 0 lies inside the lane when another change follows.
+  int n_in = 0, last_keyed = 0;
+#pragma unroll
+  for (int j = 1; j < SPL; ++j) {
+    if (key[j] != key[j - 1]) {
+      n_in += last_keyed;
+      last_keyed = key[j] >= 0 ? 1 : 0;
+    }
+  }
+  int r_in = 0;
+  const int in_base = wave_exclusive_count<3>(n_in, lane, r_in);
+
+  double acc[NV];
+  double head[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    acc[c] = v[0][c];
+    head[c] = 0.0;
+  }
+  int cur = key[0];
+  int hk = -1;
+  bool single = true;
+  int slot = in_base;
+#pragma unroll
+  for (int j = 1; j < SPL; ++j) {
+    if (key[j] != cur) {
+      if (single) {
+        hk = cur;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) head[c] = acc[c];
+        single = false;
+      } else if (cur >= 0) {
+        if (slot < CAP) {
+          skey[slot] = cur;
+#pragma unroll
+          for (int c = 0; c < NV; ++c) sval[slot * NV + c] = acc[c];
+        } else {
+          flush(cur, acc);
+        }
+        ++slot;
+      }
+      cur = key[j];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) acc[c] = v[j][c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) acc[c] += v[j][c];
+    }
+  }
+  const int tk = cur;
+
+  // ---- segmented inclusive scan of the lane tails (as in the direct form) -----------------
+  const int prev_tk = __shfl_up(tk, 1);
+  const bool start = (lane == 0) || !single || (prev_tk != tk);
+  double S[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) S[c] = acc[c];
+  int f = start ? 1 : 0;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    if (__ballot((!f) && lane >= d) == 0) break;  // wavefront-uniform exit
+    double up[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) up[c] = __shfl_up(S[c], d);
+    const int fup = __shfl_up(f, d);
+    if (lane >= d && !f) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) S[c] += up[c];
+      f = fup;
+    }
+  }
+
+  // ---- the lane's head and closing tail ------------------------------------------------------
+  double prevS[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) prevS[c] = __shfl_up(S[c], 1);
+  const int next_start = __shfl_down(start ? 1 : 0, 1);
+  const int next_single = __shfl_down(single ? 1 : 0, 1);
+  const int next_hk = __shfl_down(hk, 1);
+
+  const bool has_head = !single && hk >= 0;
+  if (has_head && lane > 0 && prev_tk == hk) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) head[c] += prevS[c];
+  }
+  const bool ends = (lane == 63) || next_start;
+  const bool has_tail =
+      ends && tk >= 0 && !((lane < 63) && !next_single && next_hk == tk);
+  const int n_ht = (has_head ? 1 : 0) + (has_tail ? 1 : 0);
+  int r_ht = 0;
+  int s2 = r_in + wave_exclusive_count<2>(n_ht, lane, r_ht);
+  if (has_head) {
+    if (s2 < CAP) {
+      skey[s2] = hk;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) sval[s2 * NV + c] = head[c];
+    } else {
+      flush(hk, head);
+    }
+    ++s2;
+  }
+  if (has_tail) {
+    if (s2 < CAP) {
+      skey[s2] = tk;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) sval[s2 * NV + c] = S[c];
+    } else {
+      flush(tk, S);
+    }
+  }
+
+  // ---- one listed run per lane (LDS operations of one wavefront complete in order) ---------
+  const int listed = r_in + r_ht < CAP ? r_in + r_ht : CAP;
+  for (int r = lane; r - lane < listed; r += 64) {
+    if (r < listed) {
+      double w[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) w[c] = sval[r * NV + c];
+      flush(skey[r], w);
+    }
+  }
+}
+
 template <int NV, class Flush>
 __device__ __forceinline__ void wave_merge_runs(const int (&key)[4], const double (&v)[4][NV],
                                                 const Flush& flush) {

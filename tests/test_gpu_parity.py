@@ -98,6 +98,22 @@ def test_point_parity(gpu_lib, name):
     assert np.abs(y - want).max() <= 1e-12 * max(scale, 1.0)
 
 
+@pytest.mark.parametrize("dwell", [1, 2, 3, 40])
+def test_point_parity_short_runs(gpu_lib, dwell):
+    # The scatter lists the runs each wavefront completes before flushing them, one per lane;
+    # short runs (many runs inside one lane's 8 samples) fill the list and a random pixel per
+    # sample overflows it (more than 128 runs per 512 samples: direct flushes).
+    prob = synth.make_random_small(seed=20 + dwell, n_samples=200003, n_pix=3000, n_dets=5,
+                                   lam_max=8, dwell=dwell)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob)
+    u = np.random.default_rng(dwell).standard_normal(ref.n_samples).astype(np.float32)
+    y = plan.point(_dev(u)).cpu().numpy()
+    want = O.point(ref, u.astype(np.float64))
+    scale = np.abs(want).max()
+    assert np.abs(y - want).max() <= 1e-12 * max(scale, 1.0)
+
+
 @pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini", "ground_lam8192"])
 @pytest.mark.parametrize("algo", ["auto", "direct", "fft"])
 def test_noise_weight_parity(gpu_lib, name, algo):
