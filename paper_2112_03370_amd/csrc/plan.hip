@@ -21,6 +21,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTile = 4096;        // samples per plan tile (never crossing a block edge)
 constexpr int kScanChunk = 4096;   // pixels per compaction workgroup
+constexpr int kAccLane = 8;        // consecutive samples per lane in the BJ accumulation
+constexpr int kAccListed = 64;     // listed runs per wavefront there
 
 // ---- hits + BJ blocks over global pixels ---------------------------------------------------
 
@@ -41,35 +43,42 @@ __global__ __launch_bounds__(kThreads) void k_plan_accumulate(
     int32_t* __restrict__ hits, int32_t* __restrict__ err) {
   const Tile tl = tiles[blockIdx.x];
   const BjFlush flush{B, hits};
+  // per wavefront: the runs it completes, listed before the atomics
+  __shared__ int skey[kThreads / 64][kAccListed];
+  __shared__ double sval[kThreads / 64][7 * kAccListed];
+  const int wave = static_cast<int>(threadIdx.x >> 6);
   const double c0 = tl.c0;
-  for (int off = 0; off < tl.len; off += kThreads * 4) {
-    const int o0 = off + threadIdx.x * 4;
+  for (int off = 0; off < tl.len; off += kThreads * kAccLane) {  // same trip count for all lanes
+    const int o0 = off + threadIdx.x * kAccLane;
     const int64_t i0 = tl.start + o0;
-    int gg[4];
-    float qq[4], uu[4];
-    bool in[4];
-    if (o0 + 4 <= tl.len && (i0 & 3) == 0) {  // one 16-byte load per stream
-      const int4 g4 = *reinterpret_cast<const int4*>(pix + i0);
-      const float4 q4 = *reinterpret_cast<const float4*>(wq + i0);
-      const float4 u4 = *reinterpret_cast<const float4*>(wu + i0);
-      gg[0] = g4.x; gg[1] = g4.y; gg[2] = g4.z; gg[3] = g4.w;
-      qq[0] = q4.x; qq[1] = q4.y; qq[2] = q4.z; qq[3] = q4.w;
-      uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
+    int gg[kAccLane];
+    float qq[kAccLane], uu[kAccLane];
+    bool in[kAccLane];
+    if (o0 + kAccLane <= tl.len && (i0 & 3) == 0) {  // 16-byte loads per stream
 #pragma unroll
-      for (int j = 0; j < 4; ++j) in[j] = true;
+      for (int h = 0; h < kAccLane / 4; ++h) {
+        const int4 g4 = *reinterpret_cast<const int4*>(pix + i0 + 4 * h);
+        const float4 q4 = *reinterpret_cast<const float4*>(wq + i0 + 4 * h);
+        const float4 u4 = *reinterpret_cast<const float4*>(wu + i0 + 4 * h);
+        gg[4 * h] = g4.x; gg[4 * h + 1] = g4.y; gg[4 * h + 2] = g4.z; gg[4 * h + 3] = g4.w;
+        qq[4 * h] = q4.x; qq[4 * h + 1] = q4.y; qq[4 * h + 2] = q4.z; qq[4 * h + 3] = q4.w;
+        uu[4 * h] = u4.x; uu[4 * h + 1] = u4.y; uu[4 * h + 2] = u4.z; uu[4 * h + 3] = u4.w;
+      }
+#pragma unroll
+      for (int j = 0; j < kAccLane; ++j) in[j] = true;
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kAccLane; ++j) {
         in[j] = o0 + j < tl.len;
         gg[j] = in[j] ? pix[i0 + j] : -1;
         qq[j] = in[j] ? wq[i0 + j] : 0.0f;
         uu[j] = in[j] ? wu[i0 + j] : 0.0f;
       }
     }
-    int key[4];
-    double v[4][7];
+    int key[kAccLane];
+    double v[kAccLane][7];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kAccLane; ++j) {
       key[j] = -1;
 #pragma unroll
       for (int c = 0; c < 7; ++c) v[j][c] = 0.0;
@@ -90,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_accumulate(
         v[j][6] = 1.0;
       }
     }
-    wave_merge_runs<7>(key, v, flush);
+    wave_merge_runs_listed<kAccLane, 7, kAccListed>(key, v, flush, skey[wave], sval[wave]);
   }
 }
 
