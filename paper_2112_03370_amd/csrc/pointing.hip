@@ -71,12 +71,12 @@ __global__ __launch_bounds__(kThreads) void k_unpoint(const int32_t* __restrict_
       bool other = false;
 #pragma unroll
       for (int j = 0; j < kLane; ++j) {
-        const bool is_a = key[j] == ka;
-        const double m0 = is_a ? a0 : b0, m1 = is_a ? a1 : b1, m2 = is_a ? a2 : b2;
         other |= key[j] >= 0 && key[j] != ka && key[j] != kb;
-        out[j] = key[j] < 0 ? 0.0f
-                            : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
-                                                 static_cast<double>(uu[j]) * m2);
+        // both candidate pixels' sums, then one select
+        const double q = static_cast<double>(qq[j]), u = static_cast<double>(uu[j]);
+        const double ta = a0 + q * a1 + u * a2;
+        const double tb = b0 + q * b1 + u * b2;
+        out[j] = key[j] < 0 ? 0.0f : static_cast<float>(key[j] == ka ? ta : tb);
       }
       if (other) {
 #pragma unroll

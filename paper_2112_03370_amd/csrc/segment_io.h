@@ -89,12 +89,13 @@ struct LanePointing {
 #pragma unroll
       for (int j = 0; j < S; ++j) {
         const int key = kk[j];
-        const bool is_a = key == ka;
-        const double m0 = is_a ? a0 : b0, m1 = is_a ? a1 : b1, m2 = is_a ? a2 : b2;
         other |= key >= 0 && key != ka && key != kb;
-        v[j] = key < 0 ? 0.0f
-                       : static_cast<float>(m0 + static_cast<double>(qq[j]) * m1 +
-                                            static_cast<double>(uu[j]) * m2);
+        // both candidate pixels' sums, then one select (cheaper than selecting three FP64
+        // pixel values)
+        const double q = static_cast<double>(qq[j]), u = static_cast<double>(uu[j]);
+        const double ta = a0 + q * a1 + u * a2;
+        const double tb = b0 + q * b1 + u * b2;
+        v[j] = key < 0 ? 0.0f : static_cast<float>(key == ka ? ta : tb);
       }
       if (other) {  // a third pixel inside the lane
 #pragma unroll
