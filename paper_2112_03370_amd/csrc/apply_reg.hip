@@ -39,6 +39,7 @@ constexpr int kRowB = 560;         // LDS stride of a k3 plane in the B <-> C tr
 constexpr int kLdsF = 32 * kRowB;  // floats of staging LDS
 constexpr int kLane = 8;           // consecutive samples per lane in the gather and scatter
 constexpr int kTab = 16 * kT + 8;  // symbol pairs per band in the kernel's read order
+constexpr int kW2 = 33;            // row stride of the W_512 table
 
 typedef __attribute__((address_space(1))) const void* global_ptr;
 typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -279,12 +280,18 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __shared__ __align__(16) float lds[kLdsF + 64];
   __shared__ float2 tw0[128];
   __shared__ float2 tw1[kN / 128];
-  __shared__ float2 w512[512];  // W_512^j = W_N^(64 j)
+  // W_512^(n1 k2) = W_N^(64 n1 k2) at [n1 * kW2 + k2], n1 < 16, k2 < 32: rows of 33 so that
+  // both the step-B reads (lanes across n1, slot k2 fixed) and the inverse reads (lanes across
+  // k2, n1 fixed) hit distinct banks
+  __shared__ float2 w512[16 * kW2];
   if (done != nullptr && *done) return;
   const int tid = threadIdx.x;
   if (tid < 128) tw0[tid] = tw0g[tid];
   if (tid < kN / 128) tw1[tid] = tw1g[tid];
-  w512[tid] = cmul(tw1g[tid >> 1], tw0g[(tid & 1) * 64]);
+  {
+    const int e = (tid >> 5) * (tid & 31);  // < 512
+    w512[(tid >> 5) * kW2 + (tid & 31)] = cmul(tw1g[e >> 1], tw0g[(e & 1) * 64]);
+  }
 
   const int wg = xcd_ordered(blockIdx.x, gridDim.x);
   const int col = wg % ncol;
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   transpose_ab<1>(v, lds, tid, k3b, n1b);
   dft32(v);
 #pragma unroll
-  for (int k2 = 1; k2 < 32; ++k2) v[k2] = cmul(v[k2], w512[n1b * k2]);
+  for (int k2 = 1; k2 < 32; ++k2) v[k2] = cmul(v[k2], w512[n1b * kW2 + k2]);
   transpose_bc<0>(v, lds, tk, k3b, n1b);
   transpose_bc<1>(v, lds, tk, k3b, n1b);
   // The band's symbol pairs (kTab float2, in this kernel's read order) go straight from global
@@ -407,8 +414,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   dft16_at<16>(v);
 #pragma unroll
   for (int n1 = 1; n1 < 16; ++n1) {
-    v[n1] = cmul(v[n1], w512[n1 * a2]);
-    v[16 + n1] = cmul(v[16 + n1], w512[n1 * b2]);
+    v[n1] = cmul(v[n1], w512[n1 * kW2 + a2]);
+    v[16 + n1] = cmul(v[16 + n1], w512[n1 * kW2 + b2]);
   }
   transpose_cb<0>(v, lds, tk, k3b, n1b);
   transpose_cb<1>(v, lds, tk, k3b, n1b);
