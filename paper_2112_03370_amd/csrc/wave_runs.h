@@ -121,6 +121,7 @@ __device__ __forceinline__ void wave_merge_runs_listed(const int (&key)[SPL],
                                                        const double (&v)[SPL][NV],
                                                        const Flush& flush, int* skey,
                                                        double* sval) {
+  static_assert(SPL >= 2 && SPL <= 9, "inner-run counts must fit the 3-bit wavefront prefix");
   const int lane = static_cast<int>(threadIdx.x & 63u);
 
   // ---- runs inside the lane: count, then list ---------------------------------------------
