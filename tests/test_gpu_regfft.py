@@ -133,3 +133,24 @@ def test_kernel_timing_counts_working_launches(gpu_lib):
     assert ms > 0.0
     # the scatter's FP64 atomics commit in a different order on every run
     assert float(_rel(x1.cpu().numpy(), x0.cpu().numpy())) <= 1e-8
+
+
+@pytest.mark.parametrize("flags", [0, "lds"])
+def test_segment_order_does_not_change_products(gpu_lib, flags):
+    # With detector offsets the plan runs segments by time inside their detector, then by
+    # detector; without them, in block order.  Only the order of the FP64 atomics differs.
+    prob = synth.make_ground(cfg_id=48, n_dets=6, samples_per_det=131072, interval=32768, side=40,
+                             lam=8192, flag_frac=0.01)
+    f = gpu_lib.FLAG_LDS_FFT if flags == "lds" else 0
+    args = (_dev(prob.pix), _dev(prob.wq), _dev(prob.wu), prob.n_pix_global, prob.blk_start,
+            prob.blk_len, prob.blk_band, prob.bands)
+    timed = gpu_lib.Plan(*args, det_offset=prob.det_offset, flags=f)
+    plain = gpu_lib.Plan(*args, flags=f)
+    assert timed.info["fused"] == (1 if f else 2)
+    x = np.random.default_rng(15).standard_normal((timed.n_kept, 3))
+    y1 = timed.apply_A(_dev(x)).cpu().numpy()
+    y2 = plain.apply_A(_dev(x)).cpu().numpy()
+    assert float(_rel(y1, y2)) <= 1e-12
+    b1 = timed.rhs(_dev(prob.d[0])).cpu().numpy()
+    b2 = plain.rhs(_dev(prob.d[0])).cpu().numpy()
+    assert float(_rel(b1, b2)) <= 1e-12
