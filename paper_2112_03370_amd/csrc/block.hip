@@ -73,15 +73,32 @@ __global__ __launch_bounds__(kThreads) void k_gram(const double* __restrict__ U,
   }
 }
 
-// out[e] = sum_w partial[w][e], fixed order
+// out[e] = sum_w partial[w][e] in a fixed order: kRedEntries entries per workgroup, 16 threads
+// per entry each summing every 16th partial, then a fixed tree over the 16 sums (one thread per
+// entry walking all partials serially took ~150 us for 512 partials)
+constexpr int kRedEntries = kThreads / 16;
+
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ partial,
                                                           int nwg, int count,
                                                           double* __restrict__ out) {
-  const int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e >= count) return;
+  __shared__ double red[kThreads];
+  const int le = threadIdx.x >> 4, lw = threadIdx.x & 15;
+  const int e = blockIdx.x * kRedEntries + le;
   double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += partial[static_cast<int64_t>(w) * count + e];
-  out[e] = s;
+  if (e < count)
+    for (int w = lw; w < nwg; w += 16) s += partial[static_cast<int64_t>(w) * count + e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int h = 8; h > 0; h >>= 1) {
+    if (lw < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (lw == 0 && e < count) out[e] = red[threadIdx.x];
+}
+
+inline unsigned reduce_grid(int count) {
+  return static_cast<unsigned>((count + kRedEntries - 1) / kRedEntries);
 }
 
 // X_cols[j] += sum_i Z_i a1[i][j];  R_j -= sum_i W_i a1[i][j];  rr partial of ||R_j||^2
@@ -297,12 +314,35 @@ mm_status gram(const double* U, int tu, const double* V, int tv, int64_t nu, Blo
   const int g = gram_grid(nu);
   hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V, tv, nu, nu, ws.partial);
   const int count = tu * tv;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                     ws.partial, g, count, ws.small);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(count)), dim3(kThreads), 0, s, ws.partial, g,
+                     count, ws.small);
   MM_HIP_TRY(hipGetLastError());
   out.resize(count);
   MM_HIP_TRY(hipMemcpyAsync(out.data(), ws.small, sizeof(double) * count, hipMemcpyDeviceToHost, s));
   MM_HIP_TRY(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
+// U^T V1 and U^T V2 to the host behind one synchronization (the second product's partials
+// overwrite the first's only after the first reduction, in stream order).
+mm_status gram_pair(const double* U, int tu, const double* V1, int tv1, const double* V2, int tv2,
+                    int64_t nu, BlockWs& ws, std::vector<double>& out1, std::vector<double>& out2,
+                    hipStream_t s) {
+  const int g = gram_grid(nu);
+  const int c1 = tu * tv1, c2 = tu * tv2;
+  hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V1, tv1, nu, nu, ws.partial);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c1)), dim3(kThreads), 0, s, ws.partial, g, c1,
+                     ws.small);
+  hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V2, tv2, nu, nu, ws.partial);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c2)), dim3(kThreads), 0, s, ws.partial, g, c2,
+                     ws.small + c1);
+  MM_HIP_TRY(hipGetLastError());
+  std::vector<double> both(c1 + c2);
+  MM_HIP_TRY(hipMemcpyAsync(both.data(), ws.small, sizeof(double) * (c1 + c2),
+                            hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  out1.assign(both.begin(), both.begin() + c1);
+  out2.assign(both.begin() + c1, both.end());
   return MM_OK;
 }
 
@@ -311,7 +351,8 @@ mm_status col_norms(const double* B, const double* Y, int t, int64_t nu, BlockWs
                     std::vector<double>& out, hipStream_t s) {
   const int g = rows_grid(nu);
   MM_TM_DISPATCH(k_col_norms, t, g, s, B, t, Y, nu, ws.partial);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(kThreads), 0, s, ws.partial, g, t, ws.small);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(t)), dim3(kThreads), 0, s, ws.partial, g, t,
+                     ws.small);
   MM_HIP_TRY(hipGetLastError());
   out.resize(t);
   MM_HIP_TRY(hipMemcpyAsync(out.data(), ws.small, sizeof(double) * t, hipMemcpyDeviceToHost, s));
@@ -362,8 +403,7 @@ mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x
   int k = 0;
   while (ta > 0 && k < max_iter) {
     MM_TRY(apply_A_multi(P, Wk, ws.Z, nu, ws.W, nu, tz, s));  // W = A Z
-    MM_TRY(gram(ws.Z, tz, ws.W, tz, nu, ws, G, s));       // G = Z^T W
-    MM_TRY(gram(ws.Z, tz, ws.R, ta, nu, ws, H, s));       // H1 = Z^T R
+    MM_TRY(gram_pair(ws.Z, tz, ws.W, tz, ws.R, ta, nu, ws, G, H, s));  // G = Z^T W, H1 = Z^T R
     sym_pinv(G, tz, 1e-12, Gi);
     matmul(Gi, H, tz, ta, A);                              // a1 = G^+ H1  (tz x ta)
     MM_HIP_TRY(hipMemcpyAsync(ws.cols, act.data(), sizeof(int32_t) * ta, hipMemcpyHostToDevice, s));
@@ -372,7 +412,8 @@ mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x
     const int g = rows_grid(nu);
     MM_TM_DISPATCH(k_block_update, tz, g, s, ws.Z, ws.W, tz, ws.R, ta, nu, x, ws.cols,
                    ws.small + kMaxT * kMaxT, ws.partial);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(kThreads), 0, s, ws.partial, g, ta, ws.small);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(ta)), dim3(kThreads), 0, s, ws.partial, g,
+                       ta, ws.small);
     MM_HIP_TRY(hipGetLastError());
     std::vector<double> rr(ta);
     MM_HIP_TRY(hipMemcpyAsync(rr.data(), ws.small, sizeof(double) * ta, hipMemcpyDeviceToHost, s));
