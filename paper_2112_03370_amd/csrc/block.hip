@@ -36,40 +36,67 @@ constexpr int kThreads = 256;
 constexpr int kMaxT = 32;
 constexpr int kTileRows = 64;
 
-// partial[wg][i * tv + j] = sum over the workgroup's rows of U_i[r] V_j[r]
+// partial[wg][i * tv + j] = sum over the workgroup's rows of U_i[r] V_j[r].  With few pairs
+// (t x t <= 128) each pair gets tpp threads, each summing every tpp-th row of a tile, and a
+// fixed tree over them at the end; with more, a thread sums whole tiles for up to 4 pairs.
 __global__ __launch_bounds__(kThreads) void k_gram(const double* __restrict__ U, int tu,
                                                    int64_t ldu, const double* __restrict__ V,
                                                    int tv, int64_t ldv, int64_t n,
                                                    double* __restrict__ partial) {
   __shared__ double su[kMaxT][kTileRows + 1];
   __shared__ double sv[kMaxT][kTileRows + 1];
+  __shared__ double red[kThreads];
   const int npair = tu * tv;
+  const int ncol = tu > tv ? tu : tv;
+  int tpp = 1;  // threads per pair (power of two)
+  while (tpp < kTileRows && 2 * tpp * npair <= kThreads) tpp *= 2;
+  const int p0 = threadIdx.x / tpp, sub = threadIdx.x % tpp;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * kTileRows; r0 < n;
        r0 += static_cast<int64_t>(gridDim.x) * kTileRows) {
-    for (int e = threadIdx.x; e < kMaxT * kTileRows; e += kThreads) {
+    for (int e = threadIdx.x; e < ncol * kTileRows; e += kThreads) {
       const int col = e / kTileRows, row = e % kTileRows;
       const int64_t r = r0 + row;
       su[col][row] = (col < tu && r < n) ? U[col * ldu + r] : 0.0;
       sv[col][row] = (col < tv && r < n) ? V[col * ldv + r] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int pidx = threadIdx.x + q * kThreads;
-      if (pidx < npair) {
-        const int i = pidx / tv, j = pidx % tv;
+    if (tpp > 1) {
+      if (p0 < npair) {
+        const int i = p0 / tv, j = p0 % tv;
         double s = 0.0;
-        for (int row = 0; row < kTileRows; ++row) s += su[i][row] * sv[j][row];
-        acc[q] += s;
+        for (int row = sub; row < kTileRows; row += tpp) s += su[i][row] * sv[j][row];
+        acc[0] += s;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pidx = threadIdx.x + q * kThreads;
+        if (pidx < npair) {
+          const int i = pidx / tv, j = pidx % tv;
+          double s = 0.0;
+          for (int row = 0; row < kTileRows; ++row) s += su[i][row] * sv[j][row];
+          acc[q] += s;
+        }
       }
     }
     __syncthreads();
   }
+  if (tpp > 1) {
+    red[threadIdx.x] = acc[0];
+    __syncthreads();
+    for (int h = tpp / 2; h > 0; h >>= 1) {
+      if (sub < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (sub == 0 && p0 < npair)
+      partial[static_cast<int64_t>(blockIdx.x) * npair + p0] = red[threadIdx.x];
+  } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int pidx = threadIdx.x + q * kThreads;
-    if (pidx < npair) partial[static_cast<int64_t>(blockIdx.x) * npair + pidx] = acc[q];
+    for (int q = 0; q < 4; ++q) {
+      const int pidx = threadIdx.x + q * kThreads;
+      if (pidx < npair) partial[static_cast<int64_t>(blockIdx.x) * npair + pidx] = acc[q];
+    }
   }
 }
 
