@@ -143,12 +143,23 @@ __global__ __launch_bounds__(kThreads) void k_defl_coef(const double* __restrict
                                                         double* __restrict__ c,
                                                         const int32_t* __restrict__ done) {
   __shared__ double s[kMaxDeflation];
+  __shared__ double red[kThreads];
   if (done != nullptr && *done) return;
-  for (int i = threadIdx.x; i < m; i += kThreads) {
-    double v = 0.0;
-    for (int k = 0; k < n_chunks; ++k) v += partial[static_cast<int64_t>(k) * m + i];
-    s[i] = v;
+  // s_i = sum of the chunk partials: tpe threads per entry, each summing every tpe-th chunk,
+  // then a fixed tree (m <= 128, so tpe >= 2)
+  int tpe = 1;
+  while (tpe < 16 && 2 * tpe * m <= kThreads) tpe *= 2;
+  const int e = threadIdx.x / tpe, sub = threadIdx.x % tpe;
+  double v = 0.0;
+  if (e < m)
+    for (int k = sub; k < n_chunks; k += tpe) v += partial[static_cast<int64_t>(k) * m + e];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = tpe / 2; h > 0; h >>= 1) {
+    if (sub < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
   }
+  if (sub == 0 && e < m) s[e] = red[threadIdx.x];
   __syncthreads();
   for (int j = threadIdx.x; j < m; j += kThreads) {
     double v = 0.0;
