@@ -361,8 +361,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // partners.  All threads run the common pairing; thread 0 keeps its spectrum in a private LDS
   // slot, where lanes 0..16 of its wave redo its 17 bin pairs (two of them single bins) side by
   // side, and reloads it after the common pairing.  That keeps the common path free of a second
-  // register pairing.  The slot is written and read by one wave only, whose LDS operations
-  // complete in order.  (The side work comes before the common pairing: placed after it, the
+  // register pairing.  The slot is written and read by one wave only; wavefront-scope fences
+  // order the hand-offs between its lanes.  (The side work comes before the common pairing: placed after it, the
   // compiler's schedule no longer fits the 128 registers of two workgroups per CU.)
   {
     const float2* stab = reinterpret_cast<const float2*>(lds);  // [k1][thread], then 8 extra
@@ -372,6 +372,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
       for (int i = 0; i < 32; ++i) own[i] = v[i];
     }
+    wave_lds_sync();  // thread 0's slot is visible to lanes 0..16
     if (tid < 17) {
       // task (0, 0): bins 1024 k1, partners k1 <-> 16 - k1, bins 0 and NC/2 alone (lanes 0..8);
       // task (0, 16): bins 512 + 1024 k1, partners k1 <-> 15 - k1 (lanes 9..16)
@@ -407,6 +408,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const float2 ss = stab[k1 * kT + tid];
       spectrum_pair(v[k1], v[31 - k1], ss.x, ss.y, twiddle(tw0, tw1, ka + 1024 * k1));
     }
+    wave_lds_sync();  // lanes 0..16 have written the slot back before thread 0 reloads it
     if (tid == 0) {
 #pragma unroll
       for (int i = 0; i < 32; ++i) v[i] = own[i];

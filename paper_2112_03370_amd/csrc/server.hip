@@ -212,7 +212,65 @@ mm_status run_request(Server* S, Request* r, hipStream_t s) {
   return worst;
 }
 
-void worker(Server* S, int slot) {
+// Runs one admitted request on the slot's stream.  Never throws: any exception becomes the
+// request's status, so that nothing can reach std::terminate from a worker thread.
+mm_status serve_request(Server* S, Request* r, hipStream_t s) {
+  try {
+    if (r->work == nullptr) {
+      std::unique_ptr<Work> w(new Work());
+      const mm_status st = work_alloc(r->entry->plan, w.get());
+      if (st != MM_OK) return st;
+      r->work = w.release();
+    }
+    return run_request(S, r, s);
+  } catch (const std::bad_alloc&) {
+    return fail(MM_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(MM_ERR_HIP, std::string("internal error: ") + ex.what());
+  } catch (...) {
+    return fail(MM_ERR_HIP, "internal error: unknown exception in a serving worker");
+  }
+}
+
+// Bookkeeping after a request ran (S->mu held).  Never throws: a workspace that cannot be put
+// back in the idle pool is released instead.
+void finish_request_locked(Server* S, Request* r, mm_status st) noexcept {
+  CacheEntry* e = r->entry;
+  // the reservation covered a new workspace (if any) and the block extra: the extra is
+  // released now, a new workspace stays accounted while it lives in the idle pool
+  S->in_use -= r->extra_bytes;
+  if (r->uses_own) {
+    e->own_work_free = true;
+  } else if (r->work != nullptr) {
+    bool kept = false;
+    try {
+      e->idle.push_back(r->work);
+      kept = true;
+    } catch (...) {
+    }
+    if (!kept) {
+      S->in_use -= r->work->bytes;
+      work_free(r->work);
+      delete r->work;
+    }
+  } else {
+    S->in_use -= r->reserved - r->extra_bytes;  // allocation failed: nothing to keep
+  }
+  r->work = nullptr;
+  e->pins -= 1;
+  e->last_use = ++S->tick;
+  r->status = st;
+  try {
+    r->error = st == MM_OK ? std::string() : std::string(last_error_cstr());
+  } catch (...) {
+  }
+  r->t_end = Clock::now();
+  r->done = true;
+  S->running -= 1;
+  S->completed += 1;
+}
+
+void worker_loop(Server* S, int slot) {
   (void)hipSetDevice(S->device);
   hipStream_t s = S->streams[slot];
   while (true) {
@@ -230,54 +288,23 @@ void worker(Server* S, int slot) {
       S->running += 1;
       S->peak_running = std::max(S->peak_running, S->running);
     }
-    mm_status st = MM_OK;
-    bool fresh = false;
-    if (r->work == nullptr) {
-      Work* w = new Work();
-      st = work_alloc(r->entry->plan, w);
-      if (st == MM_OK) {
-        r->work = w;
-        fresh = true;
-      } else {
-        delete w;
-      }
-    }
-    if (st == MM_OK) {
-      try {
-        st = run_request(S, r, s);
-      } catch (const std::bad_alloc&) {
-        st = fail(MM_ERR_OOM, "host allocation failed");
-      } catch (const std::exception& ex) {
-        st = fail(MM_ERR_HIP, std::string("internal error: ") + ex.what());
-      }
-    }
-    const std::string err = st == MM_OK ? std::string() : std::string(last_error_cstr());
+    const mm_status st = serve_request(S, r, s);
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      CacheEntry* e = r->entry;
-      // the reservation covered a new workspace (if any) and the block extra: the extra is
-      // released now, a new workspace stays accounted while it lives in the idle pool
-      S->in_use -= r->extra_bytes;
-      if (r->uses_own) {
-        e->own_work_free = true;
-      } else if (r->work != nullptr) {
-        e->idle.push_back(r->work);
-      } else {
-        S->in_use -= r->reserved - r->extra_bytes;  // allocation failed: nothing to keep
-      }
-      (void)fresh;
-      r->work = nullptr;
-      e->pins -= 1;
-      e->last_use = ++S->tick;
-      r->status = st;
-      r->error = err;
-      r->t_end = Clock::now();
-      r->done = true;
-      S->running -= 1;
-      S->completed += 1;
+      finish_request_locked(S, r, st);
     }
     S->cv_work.notify_all();
     S->cv_state.notify_all();
+  }
+}
+
+// Thread body.  The loop only throws on a failure of the synchronisation primitives
+// themselves; the thread then ends (the other slots keep serving) instead of terminating the
+// process.
+void worker(Server* S, int slot) noexcept {
+  try {
+    worker_loop(S, slot);
+  } catch (...) {
   }
 }
 
@@ -312,9 +339,27 @@ extern "C" {
 mm_status mm_server_create(const mm_server_opts* opts, mm_server_t** out) {
   if (!out) return fail(MM_ERR_INVALID, "out is NULL");
   *out = nullptr;
+  std::unique_ptr<Server> S;
+  // On any failure: stop and join the workers already started and release the streams, so
+  // that no joinable std::thread is ever destroyed (which would terminate the process).
+  auto teardown = [&]() {
+    if (!S) return;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (std::thread& t : S->workers)
+      if (t.joinable()) t.join();
+    for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
+    S->workers.clear();
+    S->streams.clear();
+  };
   try {
-    auto S = std::make_unique<Server>();
-    MM_HIP_TRY(hipGetDevice(&S->device));
+    S.reset(new Server());
+    mm_status st = MM_OK;
+    hipError_t e = hipGetDevice(&S->device);
+    if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     mm_server_opts o{};
     if (opts) o = *opts;
     S->n_slots = o.n_slots > 0 ? o.n_slots : 4;
@@ -324,20 +369,35 @@ mm_status mm_server_create(const mm_server_opts* opts, mm_server_t** out) {
       S->budget = o.hbm_budget;
     } else {
       size_t free_b = 0, total_b = 0;
-      MM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+      e = hipMemGetInfo(&free_b, &total_b);
+      if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
       S->budget = static_cast<int64_t>(0.8 * static_cast<double>(free_b));
     }
-    for (int i = 0; i < S->n_slots; ++i) {
+    S->streams.reserve(static_cast<size_t>(S->n_slots));
+    S->workers.reserve(static_cast<size_t>(S->n_slots));
+    for (int i = 0; i < S->n_slots && st == MM_OK; ++i) {
       hipStream_t s = nullptr;
-      MM_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-      S->streams.push_back(s);
+      e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        st = fail(MM_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+      } else {
+        S->streams.push_back(s);
+      }
+    }
+    if (st != MM_OK) {
+      teardown();
+      return st;
     }
     Server* raw = S.get();
     for (int i = 0; i < raw->n_slots; ++i) raw->workers.emplace_back(worker, raw, i);
     *out = reinterpret_cast<mm_server_t*>(S.release());
     return MM_OK;
   } catch (const std::exception& ex) {
+    teardown();
     return fail(MM_ERR_HIP, std::string("server creation failed: ") + ex.what());
+  } catch (...) {
+    teardown();
+    return fail(MM_ERR_HIP, "server creation failed");
   }
 }
 
@@ -347,12 +407,25 @@ mm_status mm_server_destroy(mm_server_t* server) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
-    for (Request* r : S->queue)
-      finish_unrun_locked(S, r, MM_ERR_INVALID, "server destroyed before the request ran");
+    for (Request* r : S->queue) {
+      try {
+        finish_unrun_locked(S, r, MM_ERR_INVALID, "server destroyed before the request ran");
+      } catch (...) {
+        r->done = true;  // the message could not be stored; the status is set
+      }
+    }
     S->queue.clear();
   }
   S->cv_work.notify_all();
-  for (std::thread& t : S->workers) t.join();
+  for (std::thread& t : S->workers) {
+    try {
+      if (t.joinable()) t.join();
+    } catch (...) {
+      // join only fails on a thread that cannot be joined; detach so that destroying the
+      // std::thread object cannot terminate the process
+      if (t.joinable()) t.detach();
+    }
+  }
   for (auto& kv : S->cache) {
     CacheEntry* e = kv.second.get();
     for (Work* w : e->idle) {
@@ -417,6 +490,8 @@ mm_status mm_server_plan(mm_server_t* server, const mm_geometry* g, uint64_t key
       st = build_plan(g, s, &P);
     } catch (const std::bad_alloc&) {
       st = fail(MM_ERR_OOM, "host allocation failed");
+    } catch (...) {
+      st = fail(MM_ERR_HIP, "internal error while building a plan");
     }
     (void)hipStreamDestroy(s);
   }

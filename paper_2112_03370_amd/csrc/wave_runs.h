@@ -15,6 +15,16 @@
 
 namespace mm {
 
+// Orders LDS accesses of one wavefront across its lanes: what lanes wrote before the call is
+// visible to reads by other lanes of the same wavefront after it, and reads before it complete
+// before later writes to the same slots.  A wavefront-scope release/acquire fence pair around a
+// wave barrier; it must be reached by the whole wavefront (uniform control flow).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int SPL, int NV, class Flush>
 __device__ __forceinline__ void wave_merge_runs_n(const int (&key)[SPL], const double (&v)[SPL][NV],
                                                   const Flush& flush) {
@@ -136,6 +146,7 @@ __device__ __forceinline__ void wave_merge_runs_listed(const int (&key)[SPL],
   }
   int r_in = 0;
   const int in_base = wave_exclusive_count<3>(n_in, lane, r_in);
+  wave_lds_sync();  // the previous call's listed runs have been read before slots are reused
 
   double acc[NV];
   double head[NV];
@@ -236,7 +247,8 @@ __device__ __forceinline__ void wave_merge_runs_listed(const int (&key)[SPL],
     }
   }
 
-  // ---- one listed run per lane (LDS operations of one wavefront complete in order) ---------
+  // ---- one listed run per lane ---------------------------------------------------------------
+  wave_lds_sync();  // runs listed by other lanes of the wavefront are visible
   const int listed = r_in + r_ht < CAP ? r_in + r_ht : CAP;
   for (int r = lane; r - lane < listed; r += 64) {
     if (r < listed) {
