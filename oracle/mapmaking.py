@@ -38,12 +38,12 @@ import scipy.linalg as sla
 
 __all__ = [
     "OraclePlan", "build_plan", "plan_from_problem", "sample_diagonal", "hits_global",
-    "bj_blocks_global", "condition_numbers", "toeplitz_dense", "noise_weight_direct",
+    "bj_blocks_global", "condition_numbers", "noise_weight_direct",
     "noise_weight_fft", "noise_weight", "unpoint", "point", "rhs", "apply_A", "precond_bj",
     "PCGResult", "pcg", "lanczos_extremes", "binned_map", "dense_pointing",
     "dense_noise_inverse", "dense_A", "solve_dense", "default_fft_size", "block_pcg",
     "BlockPCGResult", "block_ecg", "sym_pinv", "LanczosResult", "lanczos", "Deflation",
-    "deflation_from_lanczos", "precond_2lvl",
+    "deflation_from_lanczos", "precond_2lvl", "to_fp32", "block_ecg_literal",
 ]
 
 DEFAULT_COND_MAX = 1.0e3
@@ -172,15 +172,6 @@ def plan_from_problem(prob, cond_max=DEFAULT_COND_MAX):
 # Block-diagonal banded Toeplitz N^-1  (Toeplitz algebra package, Eq. MADCAP)
 # --------------------------------------------------------------------------------------------
 
-def toeplitz_dense(n, coef):
-    """Dense n x n symmetric banded Toeplitz matrix T[i, j] = c_|i-j| for |i-j| <= lambda."""
-    coef = np.asarray(coef, np.float64)
-    col = np.zeros(n)
-    m = min(n, coef.size)
-    col[:m] = coef[:m]
-    return sla.toeplitz(col)
-
-
 def noise_weight_direct(x, plan):
     """y = N^-1 x by the definition: y_i = sum_{j in block, |i-j| <= lambda} c_|i-j| x_j inside
     each block (truncated at its edges), y_i = x_i for samples outside every block (stbmm)."""
@@ -285,15 +276,22 @@ def rhs(plan, d, method="auto"):
     return point(plan, noise_weight(d, plan, method))
 
 
+def to_fp32(v):
+    """Round to the nearest float32 and return as float64 (the rounding of a stored FP32
+    time-domain vector)."""
+    return np.asarray(v, np.float64).astype(np.float32).astype(np.float64)
+
+
 def apply_A(plan, x, method="auto", emulate_fp32=False):
     """A x = P^T N^-1 P x applied right to left: un-point, Toeplitz product, point.
-    ``emulate_fp32`` rounds P x to float32 and runs the Toeplitz product in single precision
-    (precision-floor study only)."""
+
+    ``emulate_fp32`` models single-precision time-domain storage and arithmetic (a
+    precision-floor study, not the method): the un-pointed vector is rounded to float32, the
+    Toeplitz product runs with float32 FFTs, and its result is rounded to float32 before the
+    float64 pointing sums.  Pointing sums and everything in the pixel domain stay float64."""
     t = unpoint(plan, x)
     if emulate_fp32:
-        t = t.astype(np.float32).astype(np.float64)
-        u = noise_weight(t, plan, "fft", single=True)
-        u = u.astype(np.float32).astype(np.float64)
+        u = to_fp32(noise_weight(to_fp32(t), plan, "fft", single=True))
     else:
         u = noise_weight(t, plan, method)
     return point(plan, u)
@@ -480,7 +478,8 @@ def sym_pinv(G, rtol=1e-12):
     return (V * inv) @ V.T
 
 
-def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=1e-12):
+def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=1e-12,
+              on_iter=None):
     """Enlarged-CG recurrences (Alg. 2, Orthomin variant) on t stacked right-hand sides.
 
     R_0 = B (X_0 = 0), Z_1 = M R_0; per iteration with W = A Z_k and G = Z_k^T W:
@@ -490,7 +489,8 @@ def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=
     eigen-based pseudo-inverse (rank drop below rtol * largest eigenvalue) -- a safeguard the
     paper's Cholesky square root lacks.  A column stops (its X frozen and it leaves the block)
     when ||R_j|| < eps ||B_j||: the per-column stop test of Alg. 1 applied to stacked systems.
-    With t = 1 the recurrences are those of Alg. 1."""
+    With t = 1 the recurrences are those of Alg. 1.  ``on_iter(k, X, R)`` (optional) sees the
+    stacked iterate and residual after iteration k."""
     A = apply or (lambda v: apply_A(plan, v))
     M = precond or (lambda v: precond_bj(plan, v))
     B = np.asarray(B, np.float64)
@@ -513,6 +513,8 @@ def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=
         X[active] += (Z.T @ a1).T
         R[active] -= (W.T @ a1).T
         k += 1
+        if on_iter is not None:
+            on_iter(k, X.reshape(B.shape), R.reshape(B.shape))
         rel = np.linalg.norm(R[active], axis=1) / nb[active]
         done = rel < tol
         iters[active] = k
@@ -525,6 +527,69 @@ def block_ecg(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None, rtol=
         a2 = Gi @ (W @ MR.T)
         Z = MR - (Z.T @ a2).T
         active = active[keep]
+    relres = np.where(nb > 0, np.linalg.norm(R, axis=1) / np.where(nb > 0, nb, 1.0), 0.0)
+    return BlockPCGResult(X.reshape(B.shape), iters, relres, conv, k)
+
+
+def _sym_inv_sqrt(G, rtol):
+    """G^(-1/2) of a symmetric positive semi-definite matrix by its eigen-decomposition,
+    restricted to eigenvalues above rtol * largest (the same rank rule as sym_pinv)."""
+    w, V = np.linalg.eigh(0.5 * (G + G.T))
+    keep = w > rtol * max(w.max(), 0.0) if w.size else w > 0
+    s = np.zeros_like(w)
+    s[keep] = 1.0 / np.sqrt(w[keep])
+    return (V * s) @ V.T
+
+
+def block_ecg_literal(plan, B, tol=1e-8, max_iter=10000, apply=None, precond=None,
+                      rtol=1e-12, on_iter=None):
+    """Alg. 2 (Orthomin) step by step on t stacked right-hand sides, with the search block
+    normalised explicitly:
+
+        P_k = Z_k (Z_k^T A Z_k)^(-1/2),   alpha_k = P_k^T R_(k-1),
+        X_k = X_(k-1) + P_k alpha_k,      R_k = R_(k-1) - (A P_k) alpha_k,
+        Z_(k+1) = (I - P_k P_k^T A) M R_k.
+
+    The inverse square root is taken by eigen-decomposition with the rank rule of sym_pinv (the
+    paper uses a Cholesky factor; any square root gives the same X and R, since only
+    P_k P_k^T enters them).  As in block_ecg, each column is its own right-hand side and leaves
+    the block once ||R_j|| < eps ||B_j||.  A reference for block_ecg's folded recurrences."""
+    A = apply or (lambda v: apply_A(plan, v))
+    M = precond or (lambda v: precond_bj(plan, v))
+    B = np.asarray(B, np.float64)
+    t = B.shape[0]
+    shape = B.shape[1:]
+    Bf = B.reshape(t, -1)
+    X = np.zeros_like(Bf)
+    R = Bf.copy()
+    nb = np.linalg.norm(Bf, axis=1)
+    iters = np.zeros(t, np.int64)
+    conv = nb == 0.0
+    active = np.flatnonzero(~conv)
+    # columns of the search block are stored as rows: Zr[i] is column i of Z_k
+    Zr = np.stack([M(R[j].reshape(shape)).reshape(-1) for j in active]) if active.size else R[:0]
+    k = 0
+    while active.size and k < max_iter:
+        AZ = np.stack([A(z.reshape(shape)).reshape(-1) for z in Zr])
+        S = _sym_inv_sqrt(Zr @ AZ.T, rtol)               # (Z^T A Z)^(-1/2)
+        Pr = S @ Zr                                       # rows of P_k = Z S
+        APr = S @ AZ                                      # rows of A P_k
+        alpha = Pr @ R[active].T                          # P_k^T R, [z, active]
+        X[active] += (Pr.T @ alpha).T
+        R[active] -= (APr.T @ alpha).T
+        k += 1
+        if on_iter is not None:
+            on_iter(k, X.reshape(B.shape), R.reshape(B.shape))
+        rel = np.linalg.norm(R[active], axis=1) / nb[active]
+        done = rel < tol
+        iters[active] = k
+        conv[active[done]] = True
+        keep = ~done
+        active = active[keep]
+        if not active.size:
+            break
+        MR = np.stack([M(R[j].reshape(shape)).reshape(-1) for j in active])
+        Zr = MR - (Pr.T @ (APr @ MR.T)).T                 # (I - P P^T A) M R
     relres = np.where(nb > 0, np.linalg.norm(R, axis=1) / np.where(nb > 0, nb, 1.0), 0.0)
     return BlockPCGResult(X.reshape(B.shape), iters, relres, conv, k)
 
