@@ -52,6 +52,13 @@ enum {
 
 enum { MM_TOEPLITZ_AUTO = 0, MM_TOEPLITZ_DIRECT = 1, MM_TOEPLITZ_FFT = 2 };
 
+/* mm_geometry.precision: arithmetic of the time-domain products inside the PCG loop.
+ *   MM_PRECISION_MIXED  FP32 time-domain vectors and FP32 Toeplitz arithmetic; FP64 pointing
+ *                       sums, P^T accumulation, pixel domain and CG recurrences (default).
+ *   MM_PRECISION_FP64   every product (b and A x) in FP64 throughout (slower; the reference
+ *                       precision, and the product used by the FP64 exit check). */
+enum { MM_PRECISION_MIXED = 0, MM_PRECISION_FP64 = 1 };
+
 typedef struct mm_plan mm_plan_t;
 typedef struct mm_server mm_server_t;
 
@@ -73,6 +80,17 @@ typedef struct mm_server mm_server_t;
  *               to 2^15 run in one CU's LDS (fused with the pointing products); 2^16 and 2^17
  *               (lambda up to 2^15) use a four-step transform through a device tile.
  *   flags       MM_FLAG_* bits.
+ *   precision   MM_PRECISION_*.
+ *   n_poly, n_baselines, base_start, base_len
+ *               template map-making (Eq. defFT with the Legendre baselines of Appendix A,
+ *               Eq. polytemplate): n_poly > 0 deprojects, on every baseline interval
+ *               [base_start[i], base_start[i] + base_len[i]) (HOST int64 arrays), the Legendre
+ *               polynomials of degrees 0 .. n_poly - 1, each scaled to unit norm on the
+ *               interval's sample grid.  The weights W^-1 are then diagonal: every band must
+ *               have band_ncoef = 1 (its c_0 is the weight of the block's samples; 1 outside
+ *               blocks), otherwise MM_ERR_UNSUPPORTED.  Baselines must not overlap and, when
+ *               det_offset is given, must not cross detectors.  n_poly = 0 (the default): no
+ *               templates, F_T = N^-1 (the maximum-likelihood system).
  * All pointers are read only during mm_plan and may be released afterwards.
  */
 typedef struct {
@@ -95,6 +113,12 @@ typedef struct {
   int32_t toeplitz_algo;
   int32_t fft_size;
   int32_t flags;            /* MM_FLAG_* bits, 0 = defaults */
+  int32_t precision;        /* MM_PRECISION_*, 0 = MM_PRECISION_MIXED */
+  int32_t n_poly;           /* Legendre templates per baseline, 0 = none */
+  int32_t pad0;
+  int64_t n_baselines;
+  const int64_t* base_start;
+  const int64_t* base_len;
 } mm_geometry;
 
 /* mm_geometry.flags: MM_FLAG_UNFUSED keeps the FFT path's gather, Toeplitz product and scatter
@@ -119,6 +143,9 @@ typedef struct {
   int32_t n_chunks;       /* overlap-save segments (FFT) or tiles (direct) per product */
   int32_t fused;          /* 1: gather, Toeplitz and scatter run as one kernel per segment
                              (LDS-resident FFT), 2: the same with the register-resident FFT */
+  int32_t precision;      /* MM_PRECISION_* of the plan */
+  int32_t n_poly;         /* template orders per baseline (0: maximum-likelihood system) */
+  int64_t n_baselines;
 } mm_plan_info_t;
 
 typedef struct {
@@ -134,6 +161,13 @@ typedef struct {
                              the life of the process) and later tuned solves start with it */
   int32_t precond;        /* 0 block-Jacobi M_BD; 1 two-level M_2lvl (Eq. 2lvlDef), which needs
                              mm_deflation_build on the plan and block 0/1 */
+  int32_t refine;         /* MM_PRECISION_MIXED plans, block 0/1: up to `refine` steps of
+                             iterative refinement after the solve: r = b - A x with b and A in
+                             FP64, an inner PCG on A d = r with the plan's products to the
+                             relative tolerance that brings ||r|| under tol ||b||, x += d; stops
+                             once the FP64 true residual (Eq. CGresidual) is below tol.  0: none */
+  int32_t check_fp64;     /* nonzero: report the FP64 true residual ||b - A x|| / ||b|| with
+                             b and A in FP64 (two FP64 products; implied by refine > 0) */
 } mm_solve_opts;
 
 typedef struct {
@@ -144,6 +178,11 @@ typedef struct {
   double bnorm;           /* ||b||_2 */
   double ms;              /* wall time of the solve (of the column's group when block >= 2) */
   int32_t block;          /* columns solved together with this one (1: alone) */
+  int32_t refine_steps;   /* refinement updates applied */
+  double true_relres64;   /* ||b - A x|| / ||b|| with b and A in FP64 (Eq. CGresidual), when
+                             refine > 0, check_fp64, or an MM_PRECISION_FP64 plan; else -1 */
+  int32_t inner_iterations;  /* PCG iterations of the refinement solves */
+  int32_t pad0;
 } mm_solve_info;
 
 /* mm_plan -- build the device plan: copy the pointing to the device plan, count hits, build

@@ -148,6 +148,9 @@ mm_status mm_plan_info(const mm_plan_t* plan, mm_plan_info_t* out) {
   out->n_blocks = P->n_blocks;
   out->n_chunks = P->n_chunks;
   out->fused = (P->lambda_max > 0 && P->algo == MM_TOEPLITZ_FFT && P->fused) ? (P->reg_fft ? 2 : 1) : 0;
+  out->precision = P->precision;
+  out->n_poly = P->n_poly;
+  out->n_baselines = P->n_baselines;
   return MM_OK;
 }
 
@@ -241,10 +244,13 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
   if (k > 1 && ld_d < P->n_samples) return fail(MM_ERR_INVALID, "ld_d < n_samples");
   if (k > 0 && ((P->n_samples > 0 && !d) || (P->n_kept > 0 && !x))) return fail(MM_ERR_INVALID, "NULL vector");
   if (opts && opts->tol < 0) return fail(MM_ERR_INVALID, "tol < 0");
+  if (opts && opts->refine < 0) return fail(MM_ERR_INVALID, "refine < 0");
   hipStream_t s = as_stream(stream);
   std::lock_guard<std::mutex> lock(P->mu);
   return guarded([&]() -> mm_status {
     if (opts && opts->precond != 0 && opts->precond != 1) return fail(MM_ERR_INVALID, "precond must be 0 or 1");
+    if (opts && (opts->refine > 0 || opts->check_fp64) && opts->block != 0 && opts->block != 1 && k > 1)
+      return fail(MM_ERR_UNSUPPORTED, "refine and check_fp64 apply to block 0/1 solves");
     if (opts && opts->precond == 1 && P->defl.m == 0)
       return fail(MM_ERR_INVALID, "precond = 1 needs mm_deflation_build first");
     if (opts && opts->block != 0 && opts->block != 1 && k > 0) {

@@ -500,6 +500,10 @@ mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x
     in.true_relres = bnorm[j] > 0 ? std::sqrt(tr[j]) / bnorm[j] : 0.0;
     in.ms = ms;
     in.block = block_used;
+    in.refine_steps = 0;
+    in.true_relres64 = -1.0;
+    in.inner_iterations = 0;
+    in.pad0 = 0;
   }
   return MM_OK;
 }

@@ -338,55 +338,67 @@ mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* 
   return MM_OK;
 }
 
-mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_opts* o,
-                    mm_solve_info* info, hipStream_t caller) {
-  mm_solve_opts opts{};
-  if (o) opts = *o;
-  // The legacy null stream cannot be captured: replay graphs on a plan-owned stream that
-  // waits for the caller's prior work (the solve is synchronous, so no join is needed after).
-  hipStream_t s = caller;
-  if (caller == nullptr && opts.use_graph && !P->timing.enabled) {
-    if (P->aux == nullptr) MM_HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    MM_HIP_TRY(hipStreamSynchronize(caller));
-    s = P->aux;
+namespace {
+
+// Host-side clock or HIP events for the solve's wall time (no events in allocation-free mode).
+struct SolveClock {
+  bool events = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  ~SolveClock() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   }
-  const double tol = opts.tol > 0 ? opts.tol : 1e-8;
-  const int max_iter = opts.max_iter > 0 ? opts.max_iter : 10000;
+  mm_status start(bool use_events, hipStream_t s) {
+    events = use_events;
+    if (!events) {
+      t0 = std::chrono::steady_clock::now();
+      return MM_OK;
+    }
+    MM_HIP_TRY(hipEventCreate(&e0));
+    MM_HIP_TRY(hipEventCreate(&e1));
+    MM_HIP_TRY(hipEventRecord(e0, s));
+    return MM_OK;
+  }
+  mm_status stop(hipStream_t s) {
+    if (events) MM_HIP_TRY(hipEventRecord(e1, s));
+    return MM_OK;
+  }
+  mm_status elapsed_ms(double* ms) {  // after the stream has been synchronised
+    if (!events) {
+      *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      return MM_OK;
+    }
+    float f = 0.0f;
+    MM_HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+    *ms = f;
+    return MM_OK;
+  }
+};
+
+}  // namespace
+
+mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStream_t s,
+                      CgState* out) {
   const int nrb = W.nrb;
   const int64_t nk = P->n_kept;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  MM_HIP_TRY(hipEventCreate(&ev0));
-  MM_HIP_TRY(hipEventCreate(&ev1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-    }
-  } evg{ev0, ev1};
-  MM_HIP_TRY(hipEventRecord(ev0, s));
-
-  // b = P^T N^-1 d
-  if (P->timing.enabled) P->timing.tag = 0;
-  MM_TRY(compute_rhs(P, W, d, W.b, s));
-  if (opts.use_x0) MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
+  if (prm.use_x0) MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
   hipLaunchKernelGGL(k_init, dim3(nrb), dim3(kThreads), 0, s, P->minv, W.b, W.q, W.r, W.z,
-                     W.p, W.q, x, opts.use_x0 ? 1 : 0, nk, W.partial, nrb);
-  const bool two_level = opts.precond == 1;
-  if (two_level) {
+                     W.p, W.q, x, prm.use_x0 ? 1 : 0, nk, W.partial, nrb);
+  if (prm.two_level) {
     if (P->defl.m == 0) return fail(MM_ERR_INVALID, "precond = 1 needs a deflation space");
     MM_TRY(deflation_apply(P, W.r, W.z, W.p, W.partial, nrb, nullptr, s));  // z0 = p0 = M r0
   }
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb, tol,
-                     max_iter);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb,
+                     prm.tol, prm.max_iter);
   MM_HIP_TRY(hipGetLastError());
 
   // Iterate in chunks; the host reads the state between chunks.  Launches queued past
   // convergence exit at once; with per-kernel timing on they carry their iteration number and
   // are dropped from the timings afterwards, and the launches are eager (events per launch)
   // instead of graph replays.
-  int chunk = opts.check_every > 0 ? opts.check_every : 4;
-  const bool use_graph = opts.use_graph && !P->timing.enabled;
+  int chunk = prm.check_every > 0 ? prm.check_every : 4;
+  const bool use_graph = prm.use_graph && !P->timing.enabled;
   hipGraphExec_t gexec = nullptr;
   int graph_chunk = 0;
   struct GraphGuard {
@@ -403,7 +415,7 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
     MM_HIP_TRY(hipMemcpyAsync(W.h_state, W.state, sizeof(CgState), hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
     if (W.h_state->done) break;
-    if (queued >= max_iter + 1) break;  // safety: the device stops at max_iter
+    if (queued >= prm.max_iter + 1) break;  // safety: the device stops at max_iter
     if (use_graph) {
       if (gexec == nullptr || graph_chunk != chunk) {
         if (gexec) {
@@ -416,7 +428,7 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
         std::shared_lock<std::shared_mutex> gate(alloc_gate());
         MM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         mm_status st = MM_OK;
-        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, two_level, s);
+        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, prm.two_level, s);
         hipError_t ce = hipStreamEndCapture(s, &graph);
         gate.unlock();
         if (st != MM_OK) {
@@ -438,32 +450,71 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
     } else {
       for (int i = 0; i < chunk; ++i) {
         if (P->timing.enabled) P->timing.tag = queued + i + 1;
-        MM_TRY(iteration(P, W, x, two_level, s));
+        MM_TRY(iteration(P, W, x, prm.two_level, s));
       }
       if (P->timing.enabled) P->timing.tag = 0;
     }
     queued += chunk;
-    if (opts.check_every <= 0 && chunk < 16) chunk *= 2;
+    if (prm.check_every <= 0 && chunk < 16) chunk *= 2;
   }
+  *out = *W.h_state;
+  if (P->timing.enabled) timing_drop_after(P, out->iter);
+  return MM_OK;
+}
+
+mm_status residual_norm2(Plan* P, Work& W, const double* x, double* rr, hipStream_t s) {
+  const int nrb = W.nrb;
+  const int64_t nk = P->n_kept;
+  *rr = 0.0;
+  if (nk == 0) return MM_OK;
+  MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
+  hipLaunchKernelGGL(k_resid, dim3(nrb), dim3(kThreads), 0, s, W.b, W.q, 3 * nk, W.partial);
+  hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kThreads), 0, s, &W.state->spare, W.partial,
+                     nrb);
+  MM_HIP_TRY(hipGetLastError());
+  MM_HIP_TRY(hipMemcpyAsync(&W.h_state->spare, &W.state->spare, sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  *rr = W.h_state->spare;
+  return MM_OK;
+}
+
+mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_opts* o,
+                    mm_solve_info* info, hipStream_t caller, bool alloc_free) {
+  mm_solve_opts opts{};
+  if (o) opts = *o;
+  if (alloc_free) opts.use_graph = 0;  // instantiating a graph allocates
+  // The legacy null stream cannot be captured: replay graphs on a plan-owned stream that
+  // waits for the caller's prior work (the solve is synchronous, so no join is needed after).
+  hipStream_t s = caller;
+  if (caller == nullptr && opts.use_graph && !P->timing.enabled) {
+    if (P->aux == nullptr) MM_HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+    MM_HIP_TRY(hipStreamSynchronize(caller));
+    s = P->aux;
+  }
+  PcgParams prm;
+  prm.tol = opts.tol > 0 ? opts.tol : 1e-8;
+  prm.max_iter = opts.max_iter > 0 ? opts.max_iter : 10000;
+  prm.use_x0 = opts.use_x0 != 0;
+  prm.check_every = opts.check_every;
+  prm.use_graph = opts.use_graph != 0;
+  prm.two_level = opts.precond == 1;
+  SolveClock clock;
+  MM_TRY(clock.start(!alloc_free, s));
+
+  // b = P^T N^-1 d
+  if (P->timing.enabled) P->timing.tag = 0;
+  MM_TRY(compute_rhs(P, W, d, W.b, s));
+  CgState st{};
+  MM_TRY(pcg_iterate(P, W, x, prm, s, &st));
 
   // True residual with one more product.
-  const CgState st = *W.h_state;
-  if (P->timing.enabled) timing_drop_after(P, st.iter);
   double true_rr = 0.0;
-  if (nk > 0 && st.bb > 0.0) {
-    MM_TRY(apply_A(P, W, x, W.q, nullptr, s));
-    hipLaunchKernelGGL(k_resid, dim3(nrb), dim3(kThreads), 0, s, W.b, W.q, 3 * nk, W.partial);
-    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kThreads), 0, s, &W.state->spare, W.partial,
-                       nrb);
-    MM_HIP_TRY(hipGetLastError());
-    MM_HIP_TRY(hipMemcpyAsync(&W.h_state->spare, &W.state->spare, sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-  }
-  MM_HIP_TRY(hipEventRecord(ev1, s));
+  if (st.bb > 0.0) MM_TRY(residual_norm2(P, W, x, &true_rr, s));
+  MM_TRY(clock.stop(s));
   MM_HIP_TRY(hipStreamSynchronize(s));
-  true_rr = W.h_state->spare;
-  float ms = 0.0f;
-  MM_HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+  double ms = 0.0;
+  MM_TRY(clock.elapsed_ms(&ms));
   if (info) {
     info->iterations = st.iter;
     info->converged = st.done == 1 ? 1 : 0;
@@ -472,6 +523,10 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
     info->true_relres = st.bb > 0 ? std::sqrt(true_rr / st.bb) : 0.0;
     info->ms = ms;
     info->block = 1;
+    info->refine_steps = 0;
+    info->true_relres64 = -1.0;
+    info->inner_iterations = 0;
+    info->pad0 = 0;
   }
   if (st.done == 2) return fail(MM_ERR_NOT_SPD, "PCG breakdown: p^T A p <= 0 or r^T z <= 0");
   if (st.done != 1) return fail(MM_ERR_NO_CONV, "PCG reached max_iter without converging");

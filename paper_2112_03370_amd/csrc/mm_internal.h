@@ -127,6 +127,10 @@ struct Deflation {
 };
 
 struct Plan;
+// Time-domain work vectors are needed by unfused and direct products (plan.hip).
+bool needs_time_buffers(const Plan* P);
+// Workgroups of the pixel-domain reductions for n_kept pixels (the partials hold 4 x that).
+int32_t reduction_blocks(int64_t n_kept);
 int64_t work_bytes(const Plan* P);
 mm_status work_alloc(const Plan* P, Work* W);
 void work_free(Work* W);
@@ -151,6 +155,9 @@ struct Plan {
   int32_t n_blocks = 0;
   int32_t n_bands = 0;
   int64_t device_bytes = 0;
+  int32_t precision = MM_PRECISION_MIXED;
+  int32_t n_poly = 0;           // template map-making: Legendre orders per baseline
+  int64_t n_baselines = 0;
 
   // pointing (device)
   int32_t* lpix = nullptr;  // local pixel or -1
@@ -286,9 +293,24 @@ mm_status deflation_apply(Plan* P, const double* r, double* z, double* p, double
 mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out);
 void destroy_plan(Plan* P);  // releases the device memory and deletes P
 
-// PCG (cg.hip).
+// PCG (cg.hip).  alloc_free: no device or host allocation inside the call (no graphs, no
+// events, no plan-owned stream); W then holds caller-provided buffers.
 mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_opts* o,
-                    mm_solve_info* info, hipStream_t s);
+                    mm_solve_info* info, hipStream_t s, bool alloc_free = false);
+struct PcgParams {
+  double tol = 1e-8;
+  int32_t max_iter = 10000;
+  bool use_x0 = false;
+  int32_t check_every = 0;
+  bool use_graph = true;
+  bool two_level = false;
+};
+// Alg. 1 on the right-hand side already in W.b (x in/out); the final device state is copied
+// to *out.  Synchronous.
+mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStream_t s,
+                      CgState* out);
+// ||W.b - A x||^2 with the plan's product (uses W.q and the partials).  Synchronous.
+mm_status residual_norm2(Plan* P, Work& W, const double* x, double* rr, hipStream_t s);
 
 // FFT sizing helpers (toeplitz.hip).
 int32_t choose_fft_size(int32_t lambda_max);

@@ -548,11 +548,11 @@ void dev_free(void* p) {
   (void)hipFree(p);
 }
 
-static bool needs_time_buffers(const Plan* P) {
+bool needs_time_buffers(const Plan* P) {
   return P->lambda_max > 0 && !(P->algo == MM_TOEPLITZ_FFT && P->fused);
 }
 
-static int32_t reduction_blocks(int64_t n_kept) {
+int32_t reduction_blocks(int64_t n_kept) {
   int64_t nrb = (n_kept + 1023) / 1024;
   return static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(nrb, 1), 1024));
 }
@@ -647,6 +647,14 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   int32_t lambda_max = 0;
   MM_TRY(validate(g, order, lambda_max));
 
+  if (g->precision != MM_PRECISION_MIXED && g->precision != MM_PRECISION_FP64)
+    return fail(MM_ERR_INVALID, "unknown precision");
+  if (g->n_poly < 0) return fail(MM_ERR_INVALID, "n_poly < 0");
+  if (g->precision == MM_PRECISION_FP64)
+    return fail(MM_ERR_UNSUPPORTED, "MM_PRECISION_FP64 plans are not available in this build");
+  if (g->n_poly > 0)
+    return fail(MM_ERR_UNSUPPORTED, "template map-making is not available in this build");
+
   // Algorithm selection.
   int32_t algo = g->toeplitz_algo;
   int32_t fft_n = 0;
@@ -679,6 +687,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   P->fft_n = fft_n;
   P->n_blocks = g->n_blocks;
   P->n_bands = g->n_bands;
+  P->precision = g->precision;
   const int64_t n = g->n_samples;
   const int64_t ng = g->n_pix_global;
 

@@ -26,6 +26,7 @@ STATUS = {
 TOEPLITZ_AUTO, TOEPLITZ_DIRECT, TOEPLITZ_FFT = 0, 1, 2
 FLAG_UNFUSED = 1
 FLAG_LDS_FFT = 2
+PRECISION_MIXED, PRECISION_FP64 = 0, 1
 KIND_UNPOINT, KIND_TOEPLITZ, KIND_POINT, KIND_CG = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -45,6 +46,8 @@ class Geometry(ctypes.Structure):
         ("blk_band", _vp), ("n_bands", _c_i32), ("band_ncoef", _vp), ("band_offset", _vp),
         ("band_coef", _vp), ("n_dets", _c_i32), ("det_offset", _vp), ("cond_max", _c_dbl),
         ("toeplitz_algo", _c_i32), ("fft_size", _c_i32), ("flags", _c_i32),
+        ("precision", _c_i32), ("n_poly", _c_i32), ("pad0", _c_i32), ("n_baselines", _c_i64),
+        ("base_start", _vp), ("base_len", _vp),
     ]
 
 
@@ -54,21 +57,24 @@ class PlanInfo(ctypes.Structure):
         ("n_excised", _c_i64), ("n_gap_samples", _c_i64), ("device_bytes", _c_i64),
         ("lambda_max", _c_i32), ("toeplitz_algo", _c_i32), ("fft_size", _c_i32),
         ("n_blocks", _c_i32), ("n_chunks", _c_i32), ("fused", _c_i32),
+        ("precision", _c_i32), ("n_poly", _c_i32), ("n_baselines", _c_i64),
     ]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", _c_dbl), ("max_iter", _c_i32), ("use_x0", _c_i32),
                 ("check_every", _c_i32), ("use_graph", _c_i32), ("block", _c_i32),
-                ("precond", _c_i32)]
+                ("precond", _c_i32), ("refine", _c_i32), ("check_fp64", _c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", _c_i32), ("converged", _c_i32), ("relres", _c_dbl),
-                ("true_relres", _c_dbl), ("bnorm", _c_dbl), ("ms", _c_dbl), ("block", _c_i32)]
+                ("true_relres", _c_dbl), ("bnorm", _c_dbl), ("ms", _c_dbl), ("block", _c_i32),
+                ("refine_steps", _c_i32), ("true_relres64", _c_dbl),
+                ("inner_iterations", _c_i32), ("pad0", _c_i32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
 
 
 class DeflationInfo(ctypes.Structure):
@@ -175,7 +181,8 @@ def _host(a, dtype):
 
 
 def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
-                  det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0, flags=0):
+                  det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0, flags=0,
+                  precision=PRECISION_MIXED, n_poly=0, base_start=None, base_len=None):
     """mm_geometry for device pointing tensors and host tables; returns (Geometry, keep-alive
     list of the host arrays it points into)."""
     import torch
@@ -215,7 +222,16 @@ def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands
     g.toeplitz_algo = int(toeplitz_algo)
     g.fft_size = int(fft_size)
     g.flags = int(flags)
-    return g, [bs, bl, bb, ncoef, off, coef, det, pix, wq, wu]
+    g.precision = int(precision)
+    g.n_poly = int(n_poly)
+    bst = _host(base_start if base_start is not None else [], np.int64)
+    bln = _host(base_len if base_len is not None else [], np.int64)
+    if bst.size != bln.size:
+        raise ValueError("base_start and base_len sizes differ")
+    g.n_baselines = int(bst.size)
+    g.base_start = bst.ctypes.data if bst.size else None
+    g.base_len = bln.ctypes.data if bln.size else None
+    return g, [bs, bl, bb, ncoef, off, coef, det, pix, wq, wu, bst, bln]
 
 
 class Plan:
@@ -223,13 +239,15 @@ class Plan:
 
     def __init__(self, pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
                  det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0,
-                 flags=0, stream=None):
+                 flags=0, precision=PRECISION_MIXED, n_poly=0, base_start=None, base_len=None,
+                 stream=None):
         lib = load()
         self._lib = lib
         self.device = pix.device
         n = int(pix.numel())
         g, self._keep = make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band,
-                                      bands, det_offset, cond_max, toeplitz_algo, fft_size, flags)
+                                      bands, det_offset, cond_max, toeplitz_algo, fft_size, flags,
+                                      precision, n_poly, base_start, base_len)
         h = _vp()
         self._h = None
         check(lib.mm_plan(ctypes.byref(g), _stream(stream), ctypes.byref(h)))
@@ -313,14 +331,17 @@ class Plan:
         return z
 
     def pcg_solve(self, d, x=None, tol=1e-8, max_iter=10000, use_x0=False, check_every=0,
-                  use_graph=True, block=0, precond=0, stream=None, raise_on_error=True):
+                  use_graph=True, block=0, precond=0, refine=0, check_fp64=False, stream=None,
+                  raise_on_error=True):
         """block 0/1: PCG per column; >= 2: columns solved together in groups of `block` by the
-        enlarged-CG recurrences; < 0: group size tuned among 8, 16, 32."""
+        enlarged-CG recurrences; < 0: group size tuned among 8, 16, 32.  refine > 0: up to that
+        many FP64 refinement steps; check_fp64: report the FP64 true residual."""
         k = 1 if d.dim() == 1 else int(d.shape[0])
         ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
         x = x if x is not None else self._map(k)
         o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every,
-                      use_graph=int(use_graph), block=int(block), precond=int(precond))
+                      use_graph=int(use_graph), block=int(block), precond=int(precond),
+                      refine=int(refine), check_fp64=int(bool(check_fp64)))
         infos = (SolveInfo * max(1, k))()
         st = self._lib.mm_pcg_solve(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o), infos,
                                     _stream(stream))

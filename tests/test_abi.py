@@ -71,6 +71,10 @@ int main(void) {
   P(mm_server_stats_t, n_plans)
   printf("mm_deflation_info_t %zu\n", sizeof(mm_deflation_info_t));
   P(mm_deflation_info_t, build_ms) P(mm_deflation_info_t, device_bytes) P(mm_solve_opts, precond)
+  P(mm_geometry, precision) P(mm_geometry, n_poly) P(mm_geometry, n_baselines)
+  P(mm_geometry, base_len) P(mm_plan_info_t, precision) P(mm_plan_info_t, n_baselines)
+  P(mm_solve_opts, refine) P(mm_solve_opts, check_fp64) P(mm_solve_info, refine_steps)
+  P(mm_solve_info, true_relres64) P(mm_solve_info, inner_iterations)
   return 0;
 }
 """
@@ -110,5 +114,16 @@ int main(void) {
         "mm_deflation_info_t.build_ms": M.DeflationInfo.build_ms.offset,
         "mm_deflation_info_t.device_bytes": M.DeflationInfo.device_bytes.offset,
         "mm_solve_opts.precond": M.SolveOpts.precond.offset,
+        "mm_geometry.precision": M.Geometry.precision.offset,
+        "mm_geometry.n_poly": M.Geometry.n_poly.offset,
+        "mm_geometry.n_baselines": M.Geometry.n_baselines.offset,
+        "mm_geometry.base_len": M.Geometry.base_len.offset,
+        "mm_plan_info_t.precision": M.PlanInfo.precision.offset,
+        "mm_plan_info_t.n_baselines": M.PlanInfo.n_baselines.offset,
+        "mm_solve_opts.refine": M.SolveOpts.refine.offset,
+        "mm_solve_opts.check_fp64": M.SolveOpts.check_fp64.offset,
+        "mm_solve_info.refine_steps": M.SolveInfo.refine_steps.offset,
+        "mm_solve_info.true_relres64": M.SolveInfo.true_relres64.offset,
+        "mm_solve_info.inner_iterations": M.SolveInfo.inner_iterations.offset,
     }
     assert {k: int(v) for k, v in got.items()} == exp
