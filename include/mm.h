@@ -247,6 +247,22 @@ mm_status mm_pcg_solve(const mm_plan_t* plan, const float* d, int32_t k, int64_t
                        double* x, const mm_solve_opts* opts, mm_solve_info* info,
                        void* stream);
 
+/* mm_pcg_solve_noalloc -- mm_pcg_solve for callers that cannot allocate device memory
+ * (serving loops with a fixed footprint, code run where hipMalloc is forbidden).  It allocates
+ * nothing: the solve's pixel-domain vectors, reduction partials and device scalars live in a
+ * static device array of the library (64 MiB per GPU, held until the process ends), so
+ * 40 * n_kept bytes (five FP64 vectors of 3 n_kept) plus a few KB must fit: MM_ERR_INVALID
+ * beyond that.  Same arguments and results as mm_pcg_solve, restricted to PCG per column
+ * with block-Jacobi (opts->block 0/1, precond 0, refine 0, check_fp64 0; use_graph is
+ * ignored: launches are eager) on plans whose product keeps the time domain on chip (fused
+ * FFT product or diagonal weights, MM_PRECISION_MIXED, no templates); otherwise
+ * MM_ERR_UNSUPPORTED.  Per-kernel timing must be off.  All calls on one GPU share its array:
+ * calls are serialised per device inside the process; concurrent calls are therefore safe
+ * but never overlap.  Synchronous. */
+mm_status mm_pcg_solve_noalloc(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d,
+                               double* x, const mm_solve_opts* opts, mm_solve_info* info,
+                               void* stream);
+
 /* ---- Two-level a posteriori preconditioner (Eq. 2lvlDef, A-DEF1; Alg. 3) ------------------
  * mm_deflation_build runs m steps of Lanczos (Alg. 3) on A = P^T N^-1 P from r0 = b =
  * P^T N^-1 d (d: one right-hand side, DEVICE float [n_samples]), keeps the Lanczos vectors

@@ -132,6 +132,8 @@ def load(path: Optional[str] = None):
         "mm_apply_A": [_vp, _vp, _vp, _c_i32, _vp],
         "mm_precond_bj": [_vp, _vp, _vp, _c_i32, _vp],
         "mm_pcg_solve": [_vp, _vp, _c_i32, _c_i64, _vp, P(SolveOpts), P(SolveInfo), _vp],
+        "mm_pcg_solve_noalloc": [_vp, _vp, _c_i32, _c_i64, _vp, P(SolveOpts), P(SolveInfo),
+                                 _vp],
         "mm_set_timing": [_vp, _c_i32],
         "mm_kernel_time": [_vp, _c_i32, P(_c_dbl), P(_c_i64)],
         "mm_deflation_build": [_vp, _vp, _c_i32, _vp],
@@ -345,6 +347,23 @@ class Plan:
         infos = (SolveInfo * max(1, k))()
         st = self._lib.mm_pcg_solve(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o), infos,
                                     _stream(stream))
+        if raise_on_error:
+            check(st)
+        res = [infos[j].as_dict() for j in range(k)]
+        for r in res:
+            r["status"] = STATUS.get(st, st)
+        return x, (res[0] if k == 1 else res)
+
+    def pcg_solve_noalloc(self, d, x, tol=1e-8, max_iter=10000, use_x0=False, check_every=0,
+                          stream=None, raise_on_error=True):
+        """mm_pcg_solve_noalloc: PCG per column with the library's static scratch (x must be
+        allocated by the caller)."""
+        k = 1 if d.dim() == 1 else int(d.shape[0])
+        ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
+        o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every)
+        infos = (SolveInfo * max(1, k))()
+        st = self._lib.mm_pcg_solve_noalloc(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o),
+                                            infos, _stream(stream))
         if raise_on_error:
             check(st)
         res = [infos[j].as_dict() for j in range(k)]
