@@ -9,4 +9,5 @@ silent the oracle takes a documented reading (listed in the repository's design 
 """
 
 from .mapmaking import *  # noqa: F401,F403
-from .mapmaking import __all__  # noqa: F401
+from .templates import *  # noqa: F401,F403
+from . import mapmaking, templates  # noqa: F401

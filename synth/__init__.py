@@ -12,6 +12,7 @@ from .problems import (  # noqa: F401
     make_ground,
     make_satellite,
     make_random_small,
+    make_templates,
     make_config,
     serving_pool,
     serving_trace,

@@ -445,6 +445,56 @@ def make_random_small(seed=0, n_samples=3000, n_pix=40, n_dets=3, lam_max=16, fl
                    det_offset, m_true, dict(cfg_id=cfg, kind="random", seed=seed))
 
 
+def make_templates(cfg_id=5, n_dets=4, samples_per_det=1 << 16, interval=1 << 14, side=32,
+                   dwell=8, baseline=1000, n_poly=3, drift_sigma=5.0, sigma_range=(0.5, 2.0),
+                   cover=1.0, flag_frac=0.0, n_rhs=1, name="templates"):
+    """Ground-like sweeps for template map-making (Eq. dataModel with T = polynomial baselines).
+
+    Geometry of ``make_ground``.  White noise with a detector-dependent sigma ~ U[sigma_range],
+    hence diagonal weights: one band per detector with lambda = 0 and c_0 = 1 / sigma^2.
+    Baselines of ``baseline`` samples tile every stationary interval (the last one of an
+    interval is shorter); with ``cover < 1`` each baseline is kept with that probability and the
+    others stay uncovered.  Every kept baseline carries a drift: a polynomial of degree
+    < n_poly in the sample index with Gaussian coefficients of scale drift_sigma (the
+    low-frequency contribution that the templates describe).  Returns the Problem with
+    ``meta["base_start"]``, ``meta["base_len"]`` (int64) and ``meta["n_poly"]``.
+    """
+    geo = make_ground(cfg_id=cfg_id, n_dets=n_dets, samples_per_det=samples_per_det,
+                      interval=interval, side=side, dwell=dwell, lam=0, noise="white",
+                      flag_frac=flag_frac, n_rhs=n_rhs, name=name)
+    g = _rng(cfg_id, _S_LAYOUT)
+    sig = g.uniform(*sigma_range, size=n_dets)
+    bands = [np.array([1.0 / (s * s)], np.float32) for s in sig]
+    starts, lens = [], []
+    for s0, L in zip(geo.blk_start, geo.blk_len):
+        for o in range(0, int(L), baseline):
+            if cover >= 1.0 or g.random() < cover:
+                starts.append(int(s0) + o)
+                lens.append(min(baseline, int(L) - o))
+    base_start = np.asarray(starts, np.int64)
+    base_len = np.asarray(lens, np.int64)
+    ok = geo.pix >= 0
+    pp = np.where(ok, geo.pix, 0)
+    d = np.empty((n_rhs, geo.n_samples), np.float32)
+    wq = geo.wq.astype(np.float64)
+    wu = geo.wu.astype(np.float64)
+    for j in range(n_rhs):
+        m = geo.m_true[j]
+        sky = np.where(ok, m[pp, 0] + wq * m[pp, 1] + wu * m[pp, 2], 0.0)
+        noise = _rng(cfg_id, _S_NOISE, 0, 0, j).standard_normal(geo.n_samples)
+        det = np.searchsorted(geo.det_offset, np.arange(geo.n_samples), side="right") - 1
+        drift = np.zeros(geo.n_samples)
+        coef = _rng(cfg_id, _S_NOISE, 1, 0, j).standard_normal((len(starts), max(1, n_poly)))
+        for i, (s0, L) in enumerate(zip(starts, lens)):
+            u = np.arange(L) / max(1, L) - 0.5
+            drift[s0:s0 + L] = np.polynomial.polynomial.polyval(u, drift_sigma * coef[i, :n_poly])
+        d[j] = (sky + sig[det] * noise + drift).astype(np.float32)
+    meta = dict(geo.meta, kind="templates", base_start=base_start, base_len=base_len,
+                n_poly=n_poly, sigmas=sig.tolist())
+    return Problem(name, geo.pix, geo.wq, geo.wu, d, geo.n_pix_global, geo.blk_start,
+                   geo.blk_len, geo.blk_band, bands, geo.det_offset, geo.m_true, meta)
+
+
 # --------------------------------------------------------------------------------------------
 # Named workloads (shapes of the benchmark configurations)
 # --------------------------------------------------------------------------------------------
