@@ -242,14 +242,43 @@ __global__ __launch_bounds__(kThreads) void k_reduce_to(double* out, const doubl
   if (threadIdx.x == 0) *out = s;
 }
 
+// out = a - q (q may be null: out = a), partials of ||out||^2 per workgroup.
+__global__ __launch_bounds__(kThreads) void k_sub_norm(const double* __restrict__ a,
+                                                       const double* __restrict__ q,
+                                                       double* __restrict__ out, int64_t n,
+                                                       double* partial) {
+  __shared__ double sh[kThreads / 64];
+  double v = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double r = q != nullptr ? a[i] - q[i] : a[i];
+    if (out != nullptr) out[i] = r;
+    v += r * r;
+  }
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_add(double* __restrict__ x,
+                                                  const double* __restrict__ dx, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    x[i] += dx[i];
+}
+
 // One PCG iteration (all launches gated by state->done).  With the two-level preconditioner,
 // z = M_2lvl r replaces the block-Jacobi z of k_update (and its <r, z> partials) before beta.
 mm_status iteration(Plan* P, Work& W, double* x, bool two_level, hipStream_t s) {
   const int32_t* done = &W.state->done;
   const int nrb = W.nrb;
   const int64_t nk = P->n_kept;
-  if (P->lambda_max == 0) {
+  if (P->n_poly > 0) {
+    MM_TRY(launch_template_apply(P, W.p, nullptr, W.q, done, s));  // q was zeroed by k_update
+  } else if (P->lambda_max == 0) {
     MM_TRY(launch_diag_apply(P, W.p, nullptr, W.q, done, s));  // q was zeroed by k_update
+  } else if (P->precision == MM_PRECISION_FP64) {
+    // synchronous and not gated by `done`: such plans run one iteration per host check
+    MM_TRY(exact_product(P, W.p, nullptr, W.q, s));
   } else if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
     MM_TRY(launch_apply_fused(P, W.p, nullptr, W.q, done, s));
   } else {
@@ -298,10 +327,15 @@ mm_status launch_precond_multi(Plan* P, const double* r, double* z, int32_t ncol
 }
 
 mm_status compute_rhs(Plan* P, Work& W, const float* d, double* b, hipStream_t s) {
+  if (P->n_poly > 0) {
+    MM_TRY(launch_zero(b, 3 * P->n_kept, s));
+    return launch_template_apply(P, nullptr, d, b, nullptr, s);
+  }
   if (P->lambda_max == 0) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
     return launch_diag_apply(P, nullptr, d, b, nullptr, s);
   }
+  if (P->precision == MM_PRECISION_FP64) return exact_product(P, nullptr, d, b, s);
   if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
     return launch_apply_fused(P, nullptr, d, b, nullptr, s);
@@ -313,10 +347,15 @@ mm_status compute_rhs(Plan* P, Work& W, const float* d, double* b, hipStream_t s
 
 mm_status apply_A(Plan* P, Work& W, const double* x, double* y, const int32_t* done,
                   hipStream_t s) {
+  if (P->n_poly > 0) {
+    MM_TRY(launch_zero(y, 3 * P->n_kept, s));
+    return launch_template_apply(P, x, nullptr, y, done, s);
+  }
   if (P->lambda_max == 0) {
     MM_TRY(launch_zero(y, 3 * P->n_kept, s));
     return launch_diag_apply(P, x, nullptr, y, done, s);
   }
+  if (P->precision == MM_PRECISION_FP64) return exact_product(P, x, nullptr, y, s);
   if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
     MM_TRY(launch_zero(y, 3 * P->n_kept, s));
     return launch_apply_fused(P, x, nullptr, y, done, s);
@@ -330,7 +369,8 @@ mm_status apply_A(Plan* P, Work& W, const double* x, double* y, const int32_t* d
 mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* y, int64_t ldy,
                         int32_t ncol, hipStream_t s) {
   if (ncol <= 0 || P->n_kept == 0) return MM_OK;
-  if (P->lambda_max != 0 && P->algo == MM_TOEPLITZ_FFT && P->fused) {
+  if (P->lambda_max != 0 && P->algo == MM_TOEPLITZ_FFT && P->fused &&
+      P->precision == MM_PRECISION_MIXED) {
     for (int32_t j = 0; j < ncol; ++j) MM_TRY(launch_zero(y + j * ldy, 3 * P->n_kept, s));
     return launch_apply_fused(P, x, nullptr, y, nullptr, s, ncol, ldx, ldy);
   }
@@ -397,8 +437,11 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
   // convergence exit at once; with per-kernel timing on they carry their iteration number and
   // are dropped from the timings afterwards, and the launches are eager (events per launch)
   // instead of graph replays.
-  int chunk = prm.check_every > 0 ? prm.check_every : 4;
-  const bool use_graph = prm.use_graph && !P->timing.enabled;
+  // FP64 plans: their product is synchronous and not gated by the stop flag, so the host checks
+  // after every iteration and nothing is captured
+  const bool one_by_one = P->precision == MM_PRECISION_FP64 && P->lambda_max > 0;
+  int chunk = one_by_one ? 1 : (prm.check_every > 0 ? prm.check_every : 4);
+  const bool use_graph = prm.use_graph && !P->timing.enabled && !one_by_one;
   hipGraphExec_t gexec = nullptr;
   int graph_chunk = 0;
   struct GraphGuard {
@@ -455,7 +498,7 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
       if (P->timing.enabled) P->timing.tag = 0;
     }
     queued += chunk;
-    if (prm.check_every <= 0 && chunk < 16) chunk *= 2;
+    if (prm.check_every <= 0 && chunk < 16 && !one_by_one) chunk *= 2;
   }
   *out = *W.h_state;
   if (P->timing.enabled) timing_drop_after(P, out->iter);
@@ -476,6 +519,81 @@ mm_status residual_norm2(Plan* P, Work& W, const double* x, double* rr, hipStrea
                             hipMemcpyDeviceToHost, s));
   MM_HIP_TRY(hipStreamSynchronize(s));
   *rr = W.h_state->spare;
+  return MM_OK;
+}
+
+namespace {
+
+// ||a - q||^2 (q may be null) into *out, with out_vec = a - q when given.  Synchronous.
+mm_status sub_norm2(Work& W, const double* a, const double* q, double* out_vec, int64_t n,
+                    double* out, hipStream_t s) {
+  const int nrb = W.nrb;
+  hipLaunchKernelGGL(k_sub_norm, dim3(nrb), dim3(kThreads), 0, s, a, q, out_vec, n, W.partial);
+  hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kThreads), 0, s, &W.state->spare, W.partial, nrb);
+  MM_HIP_TRY(hipGetLastError());
+  MM_HIP_TRY(hipMemcpyAsync(&W.h_state->spare, &W.state->spare, sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  *out = W.h_state->spare;
+  return MM_OK;
+}
+
+template <class T>
+struct DevVec {
+  T* p = nullptr;
+  ~DevVec() { dev_free(p); }
+  mm_status alloc(size_t n) {
+    const hipError_t e = dev_malloc(reinterpret_cast<void**>(&p), n * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(MM_ERR_OOM, std::string("hipMalloc (refinement): ") + hipGetErrorString(e));
+    }
+    return MM_OK;
+  }
+};
+
+}  // namespace
+
+// FP64 true residual of x, and up to max_steps refinement updates: r = b - A x with b and A in
+// FP64; inner PCG with the plan's own product on A dx = r to the relative tolerance that
+// brings ||r|| under tol ||b|| with a factor 2 to spare; x += dx.  Stops when the FP64
+// residual is below tol.  *rel64 is the FP64 relative residual of the returned x.
+mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgParams& outer,
+                      int32_t max_steps, hipStream_t s, double* rel64, int32_t* steps,
+                      int32_t* inner_its) {
+  const int64_t nu = 3 * P->n_kept;
+  DevVec<double> b64, dx;
+  MM_TRY(b64.alloc(static_cast<size_t>(nu)));
+  MM_TRY(exact_product(P, nullptr, d, b64.p, s));
+  double bb = 0.0;
+  MM_TRY(sub_norm2(W, b64.p, nullptr, nullptr, nu, &bb, s));
+  *steps = 0;
+  *inner_its = 0;
+  if (!(bb > 0.0)) {
+    *rel64 = 0.0;
+    return MM_OK;
+  }
+  if (max_steps > 0) MM_TRY(dx.alloc(static_cast<size_t>(nu)));
+  while (true) {
+    MM_TRY(exact_product(P, x, nullptr, W.q, s));
+    double rr = 0.0;
+    MM_TRY(sub_norm2(W, b64.p, W.q, W.b, nu, &rr, s));  // W.b = r = b - A x
+    *rel64 = std::sqrt(rr / bb);
+    if (*rel64 < outer.tol || *steps >= max_steps) break;
+    PcgParams inner = outer;
+    inner.use_x0 = false;
+    inner.two_level = outer.two_level;
+    inner.tol = std::min(0.5, std::max(1e-6, 0.5 * outer.tol / *rel64));
+    CgState st{};
+    MM_TRY(pcg_iterate(P, W, dx.p, inner, s, &st));
+    *inner_its += st.iter;
+    if (st.done == 2) return fail(MM_ERR_NOT_SPD, "refinement PCG breakdown");
+    int64_t g = (nu + kThreads - 1) / kThreads;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_add, dim3(static_cast<unsigned>(g)), dim3(kThreads), 0, s, x, dx.p, nu);
+    MM_HIP_TRY(hipGetLastError());
+    *steps += 1;
+  }
   return MM_OK;
 }
 
@@ -511,6 +629,17 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
   // True residual with one more product.
   double true_rr = 0.0;
   if (st.bb > 0.0) MM_TRY(residual_norm2(P, W, x, &true_rr, s));
+
+  // FP64 true residual (Eq. CGresidual) and iterative refinement for mixed-precision plans.
+  double rel64 = -1.0;
+  int32_t steps = 0, inner_its = 0;
+  if (P->precision == MM_PRECISION_FP64 || P->lambda_max == 0) {
+    // the products are FP64 already: the true residual above is the FP64 one
+    if (opts.refine > 0 || opts.check_fp64) rel64 = st.bb > 0 ? std::sqrt(true_rr / st.bb) : 0.0;
+  } else if ((opts.refine > 0 || opts.check_fp64) && st.bb > 0.0) {
+    if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
+    MM_TRY(refine_fp64(P, W, d, x, prm, opts.refine, s, &rel64, &steps, &inner_its));
+  }
   MM_TRY(clock.stop(s));
   MM_HIP_TRY(hipStreamSynchronize(s));
   double ms = 0.0;
@@ -523,12 +652,15 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
     info->true_relres = st.bb > 0 ? std::sqrt(true_rr / st.bb) : 0.0;
     info->ms = ms;
     info->block = 1;
-    info->refine_steps = 0;
-    info->true_relres64 = -1.0;
-    info->inner_iterations = 0;
+    info->refine_steps = steps;
+    info->true_relres64 = rel64;
+    info->inner_iterations = inner_its;
     info->pad0 = 0;
+    if (opts.refine > 0 && rel64 >= 0.0) info->converged = rel64 < prm.tol ? 1 : 0;
   }
   if (st.done == 2) return fail(MM_ERR_NOT_SPD, "PCG breakdown: p^T A p <= 0 or r^T z <= 0");
+  if (opts.refine > 0 && rel64 >= prm.tol)
+    return fail(MM_ERR_NO_CONV, "refinement did not bring the FP64 true residual under tol");
   if (st.done != 1) return fail(MM_ERR_NO_CONV, "PCG reached max_iter without converging");
   return MM_OK;
 }

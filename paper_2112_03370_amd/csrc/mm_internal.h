@@ -57,6 +57,15 @@ struct Tile {
   float c0;
 };
 
+// A template baseline (template map-making): samples [start, start + len) with the diagonal
+// weight w of the stationary interval that holds them.
+constexpr int kMaxTemplates = 8;
+struct TBase {
+  int64_t start;
+  int32_t len;
+  float w;
+};
+
 // Device-resident PCG scalars.
 struct CgState {
   double rz;        // <r, z> of the current iterate
@@ -191,6 +200,20 @@ struct Plan {
   int32_t n_id_seg = 0;
   std::vector<int64_t> h_id_seg;
 
+  // template map-making (templates.hip): baselines, pseudo-inverted kernel blocks
+  // [n_baselines][n_poly][n_poly], and the tiles of samples outside every baseline
+  TBase* tbases = nullptr;
+  double* tkinv = nullptr;
+  Tile* free_tiles = nullptr;
+  int32_t n_free_tiles = 0;
+
+  // FP64 product (exact.hip): symbol of every band at fft_n in FP64 and exp(-2 pi i k/fft_n)
+  // for k < fft_n / 2, built on first use under x_mu
+  double* x_spec = nullptr;
+  double2* x_tw = nullptr;
+  bool x_ready = false;
+  std::mutex x_mu;
+
   Work work;                    // workspace of the plain calls (serialized by mu)
   Deflation defl;               // two-level preconditioner (built on request, under mu)
   hipStream_t aux = nullptr;    // plan-owned stream for graph replay when the caller's is null
@@ -289,6 +312,20 @@ void deflation_free(Deflation* D);
 mm_status deflation_apply(Plan* P, const double* r, double* z, double* p, double* partial, int nrb,
                           const int32_t* done, hipStream_t s);
 
+// FP64 band symbols at the plan's FFT length (plan.hip).
+mm_status launch_band_symbol64(Plan* P, double* spec64, hipStream_t s);
+// FP64 product (exact.hip): y = P^T N^-1 P x (d == nullptr) or y = P^T N^-1 d (x == nullptr),
+// every step in FP64, y overwritten.  Synchronous (staging tiles are allocated per call).
+mm_status exact_product(Plan* P, const double* x, const float* d, double* y, hipStream_t s);
+
+// Template map-making (templates.hip): tables and kernel blocks at plan time (tiles: the
+// plan's weight tiles, sorted, covering every sample), and y += P^T F_T P x (d == nullptr) or
+// y += P^T F_T d (x == nullptr), FP64, done-gated.
+mm_status build_templates(Plan* P, const mm_geometry* g, const std::vector<Tile>& tiles,
+                          hipStream_t s);
+mm_status launch_template_apply(Plan* P, const double* x, const float* d, double* y,
+                                const int32_t* done, hipStream_t s);
+
 // Plan construction (plan.hip).
 mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out);
 void destroy_plan(Plan* P);  // releases the device memory and deletes P
@@ -309,6 +346,10 @@ struct PcgParams {
 // to *out.  Synchronous.
 mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStream_t s,
                       CgState* out);
+// FP64 true residual and iterative refinement after a solve (cg.hip).
+mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgParams& outer,
+                      int32_t max_steps, hipStream_t s, double* rel64, int32_t* steps,
+                      int32_t* inner_its);
 // ||W.b - A x||^2 with the plan's product (uses W.q and the partials).  Synchronous.
 mm_status residual_norm2(Plan* P, Work& W, const double* x, double* rr, hipStream_t s);
 

@@ -283,7 +283,7 @@ constexpr int kSymPts = 8;
 __global__ __launch_bounds__(kThreads) void k_band_symbol(
     const float* __restrict__ coef, const int64_t* __restrict__ off,
     const int32_t* __restrict__ ncoef, int M, int fft_n, float* __restrict__ spec,
-    double* __restrict__ block_min) {
+    double* __restrict__ spec64, double* __restrict__ block_min) {
   __shared__ double red[kThreads / 64];
   const int band = blockIdx.y;
   const int nc = ncoef[band];
@@ -332,12 +332,13 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol(
     if (k[p] > M / 2) continue;
     const double f = c0 + x[p] * b1[p] - b2[p];
     m = fmin(m, f);
-    if (spec != nullptr) {
+    if (spec != nullptr || spec64 != nullptr) {
       const int step = M / fft_n;
       if (k[p] % step == 0) {
         const int kk = k[p] / step;  // 0 .. fft_n / 2
-        spec[static_cast<int64_t>(band) * (fft_n / 2 + 1) + kk] =
-            static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
+        const int64_t at = static_cast<int64_t>(band) * (fft_n / 2 + 1) + kk;
+        if (spec != nullptr) spec[at] = static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
+        if (spec64 != nullptr) spec64[at] = f;
       }
     }
   }
@@ -365,7 +366,7 @@ constexpr int kSymR = 16;   // r values per workgroup
 __global__ __launch_bounds__(kThreads) void k_band_symbol2(
     const float* __restrict__ coef, const int64_t* __restrict__ off,
     const int32_t* __restrict__ ncoef, int M, int fft_n, float* __restrict__ spec,
-    double* __restrict__ block_min) {
+    double* __restrict__ spec64, double* __restrict__ block_min) {
   static_assert(kThreads == 256 && kSymP * kSymR == 4 * kThreads, "thread mapping");
   __shared__ double gr[kSymP * kSymR], gi[kSymP * kSymR];
   __shared__ double red[kThreads / 64];
@@ -428,11 +429,13 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol2(
       vi = ni;
     }
     m = fmin(m, f);
-    if (spec != nullptr) {
+    if (spec != nullptr || spec64 != nullptr) {
       const int step = M / fft_n;
-      if (k % step == 0)
-        spec[static_cast<int64_t>(band) * (fft_n / 2 + 1) + k / step] =
-            static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
+      if (k % step == 0) {
+        const int64_t at = static_cast<int64_t>(band) * (fft_n / 2 + 1) + k / step;
+        if (spec != nullptr) spec[at] = static_cast<float>(f / (2.0 * static_cast<double>(fft_n)));
+        if (spec64 != nullptr) spec64[at] = f;
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_down(m, o));
@@ -444,6 +447,36 @@ __global__ __launch_bounds__(kThreads) void k_band_symbol2(
     block_min[static_cast<int64_t>(band) * gridDim.x + blockIdx.x] = rm;
   }
 }
+
+}  // namespace
+
+// FP64 symbol S[k] = c_0 + 2 sum_j c_j cos(2 pi j k / N), k = 0 .. N/2, of every band at the
+// plan's FFT length N (unscaled), for the FP64 product.  Synchronous.
+mm_status launch_band_symbol64(Plan* P, double* spec64, hipStream_t s) {
+  const int M = P->fft_n;
+  if (P->n_bands == 0 || M <= 0) return MM_OK;
+  const bool two_level = M >= 4096;
+  const int gx = two_level ? M / (kSymP * kSymR)
+                           : (M / 2 + 1 + kThreads * kSymPts - 1) / (kThreads * kSymPts);
+  double* mins = nullptr;
+  const hipError_t e = dev_malloc(reinterpret_cast<void**>(&mins),
+                                  sizeof(double) * static_cast<size_t>(gx) * P->n_bands);
+  if (e != hipSuccess) return fail(MM_ERR_OOM, std::string("hipMalloc (symbol): ") + hipGetErrorString(e));
+  if (two_level)
+    hipLaunchKernelGGL(k_band_symbol2, dim3(gx, P->n_bands), dim3(kThreads), 0, s, P->band_coef,
+                       P->band_off, P->band_ncoef, M, M, static_cast<float*>(nullptr), spec64, mins);
+  else
+    hipLaunchKernelGGL(k_band_symbol, dim3(gx, P->n_bands), dim3(kThreads), 0, s, P->band_coef,
+                       P->band_off, P->band_ncoef, M, M, static_cast<float*>(nullptr), spec64, mins);
+  const hipError_t le = hipGetLastError();
+  const hipError_t se = hipStreamSynchronize(s);
+  dev_free(mins);
+  if (le != hipSuccess) return fail(MM_ERR_HIP, std::string("symbol launch: ") + hipGetErrorString(le));
+  if (se != hipSuccess) return fail(MM_ERR_HIP, std::string("symbol: ") + hipGetErrorString(se));
+  return MM_OK;
+}
+
+namespace {
 
 // Stream-ordered upload (no legacy-stream operation: other threads may be capturing graphs on
 // their own streams meanwhile); synchronous, since h is released by the caller afterwards.
@@ -630,6 +663,11 @@ void destroy_plan(Plan* P) {
                   P->spec_reg,   P->long_pq,  P->tw0,     P->tw1,      P->chunks,
                   P->tiles,      P->id_tiles, P->id_seg};
   for (void* p : ptrs) dev_free(p);
+  dev_free(P->x_spec);
+  dev_free(P->x_tw);
+  dev_free(P->tbases);
+  dev_free(P->tkinv);
+  dev_free(P->free_tiles);
   work_free(&P->work);
   deflation_free(&P->defl);
   if (P->aux) (void)hipStreamDestroy(P->aux);
@@ -650,10 +688,6 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   if (g->precision != MM_PRECISION_MIXED && g->precision != MM_PRECISION_FP64)
     return fail(MM_ERR_INVALID, "unknown precision");
   if (g->n_poly < 0) return fail(MM_ERR_INVALID, "n_poly < 0");
-  if (g->precision == MM_PRECISION_FP64)
-    return fail(MM_ERR_UNSUPPORTED, "MM_PRECISION_FP64 plans are not available in this build");
-  if (g->n_poly > 0)
-    return fail(MM_ERR_UNSUPPORTED, "template map-making is not available in this build");
 
   // Algorithm selection.
   int32_t algo = g->toeplitz_algo;
@@ -863,10 +897,12 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     MM_TRY(mins.alloc(static_cast<size_t>(gx) * g->n_bands));
     if (two_level)
       hipLaunchKernelGGL(k_band_symbol2, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
-                         P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
+                         P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec,
+                         static_cast<double*>(nullptr), mins.p);
     else
       hipLaunchKernelGGL(k_band_symbol, dim3(gx, g->n_bands), dim3(kThreads), 0, s, P->band_coef,
-                         P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec, mins.p);
+                         P->band_off, P->band_ncoef, M, fft_n > 0 ? fft_n : M, P->spec,
+                         static_cast<double*>(nullptr), mins.p);
     MM_HIP_TRY(hipGetLastError());
     std::vector<double> h_mins(static_cast<size_t>(gx) * g->n_bands);
     MM_HIP_TRY(hipMemcpyAsync(h_mins.data(), mins.p, h_mins.size() * sizeof(double),
@@ -912,6 +948,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   MM_HIP_TRY(hipMemcpyAsync(&h_gap, ctr.p + 1, sizeof(h_gap), hipMemcpyDeviceToHost, s));
   MM_HIP_TRY(hipStreamSynchronize(s));
   P->n_gap = static_cast<int64_t>(h_gap);
+  MM_TRY(build_templates(P, g, tiles, s));
   guard.keep = true;
   *out = P;
   return MM_OK;
