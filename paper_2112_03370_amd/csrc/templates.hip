@@ -1,0 +1,407 @@
+// Template map-making: the system product P^T F_T P with
+//
+//     F_T = W^-1 (I - T (T^T W^-1 T)^+ T^T W^-1)                                (Eq. defFT)
+//
+// for diagonal weights W^-1 and Legendre baselines (Appendix A, Eq. polytemplate): on every
+// baseline interval of L samples the templates are sqrt((2k+1)/L) P_k(x_j), k < n_poly, at the
+// midpoints x_j = (2j+1)/L - 1.  The orthogonalisation kernel T^T W^-1 T is block-diagonal, one
+// n_poly x n_poly block per baseline, built on the device in FP64 at plan time and
+// pseudo-inverted on the host (eigen-directions below 1e-12 of the largest dropped, the paper's
+// SVD threshold).  A baseline lies inside one stationary interval (or outside all of them), so
+// its weight w is the c_0 of that interval's band; gap samples (flagged or excised) weigh 0.
+//
+// The product runs as one kernel, one workgroup per baseline, every step in FP64:
+//   1. t_s = (P x)_s (or the data sample), weighted v_s = w t_s; projections a_k = sum_s T_sk v_s
+//      reduced over the workgroup (the time-domain projection of the templates algebra)
+//   2. c = K_b^+ a
+//   3. u_s = w (t_s - sum_k T_sk c_k)  (template projection subtracted); y += P^T u through the
+//      wavefront run merge
+// Samples of the first kCached steps of a baseline stay in registers between 1 and 3, so
+// baselines of up to kCached x 1024 samples read their pointing once; longer ones re-gather the
+// rest.  Samples outside every baseline get u = w t through the diagonal product.
+#include <algorithm>
+#include <cmath>
+
+#include "mm_internal.h"
+#include "wave_runs.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kTT = 256;          // threads per workgroup
+constexpr int kStep = 4 * kTT;    // samples per step (4 consecutive per lane)
+constexpr int kCached = 4;        // steps kept in registers
+
+struct TFlush {
+  double* y;
+  __device__ void operator()(int key, const double (&v)[3]) const {
+    double* dst = y + 3 * static_cast<int64_t>(key);
+    unsafeAtomicAdd(dst + 0, v[0]);
+    unsafeAtomicAdd(dst + 1, v[1]);
+    unsafeAtomicAdd(dst + 2, v[2]);
+  }
+};
+
+// Scaled Legendre values T_k = scale_k P_k(x), k < n, by the three-term recurrence
+// (k + 1) P_(k+1) = (2k + 1) x P_k - k P_(k-1).
+__device__ __forceinline__ void legendre(double x, int n, const double* scale,
+                                         double (&T)[kMaxTemplates]) {
+  double p0 = 1.0, p1 = x;
+#pragma unroll
+  for (int k = 0; k < kMaxTemplates; ++k) {
+    double pk;
+    if (k == 0) {
+      pk = p0;
+    } else if (k == 1) {
+      pk = p1;
+    } else {
+      pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / static_cast<double>(k);
+      p0 = p1;
+      p1 = pk;
+    }
+    T[k] = k < n ? scale[k] * pk : 0.0;
+  }
+}
+
+template <bool kData>
+__device__ __forceinline__ void load4(const int32_t* __restrict__ lpix,
+                                      const float* __restrict__ wq,
+                                      const float* __restrict__ wu,
+                                      const double* __restrict__ x,
+                                      const float* __restrict__ d, int64_t start, int len,
+                                      int j0, int (&key)[4], double (&t)[4], double (&q)[4],
+                                      double (&u)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = j0 + i;
+    key[i] = -1;
+    t[i] = q[i] = u[i] = 0.0;
+    if (j < len) {
+      const int64_t g = start + j;
+      const int p = lpix[g];
+      if (p >= 0) {
+        key[i] = p;
+        q[i] = static_cast<double>(wq[g]);
+        u[i] = static_cast<double>(wu[g]);
+        if (kData) {
+          t[i] = static_cast<double>(d[g]);
+        } else {
+          const double* m = x + 3 * static_cast<int64_t>(p);
+          t[i] = m[0] + q[i] * m[1] + u[i] * m[2];
+        }
+      }
+    }
+  }
+}
+
+// Projections of 4 samples onto the templates: a_k += T_k(x_j) w t_j.
+__device__ __forceinline__ void project4(const int (&key)[4], const double (&t)[4], int j0,
+                                         double invL, double w, int n, const double* scale,
+                                         double (&a)[kMaxTemplates]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (key[i] < 0) continue;
+    double T[kMaxTemplates];
+    legendre(fma(2.0, static_cast<double>(j0 + i), 1.0) * invL - 1.0, n, scale, T);
+    const double v = w * t[i];
+#pragma unroll
+    for (int k = 0; k < kMaxTemplates; ++k) a[k] = fma(T[k], v, a[k]);
+  }
+}
+
+// u_j = w (t_j - sum_k T_k c_k) for 4 samples, then the pointing sums.
+__device__ __forceinline__ void subtract_point4(const int (&key)[4], const double (&t)[4],
+                                                const double (&q)[4], const double (&u)[4],
+                                                int j0, double invL, double w, int n,
+                                                const double* scale, const double* c,
+                                                double* y) {
+  double v[4][3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double r = 0.0;
+    if (key[i] >= 0) {
+      double T[kMaxTemplates];
+      legendre(fma(2.0, static_cast<double>(j0 + i), 1.0) * invL - 1.0, n, scale, T);
+      double fit = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxTemplates; ++k) fit = fma(T[k], c[k], fit);
+      r = w * (t[i] - fit);
+    }
+    v[i][0] = r;
+    v[i][1] = q[i] * r;
+    v[i][2] = u[i] * r;
+  }
+  wave_merge_runs<3>(key, v, TFlush{y});
+}
+
+template <bool kData>
+__global__ __launch_bounds__(kTT) void k_template_apply(
+    const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
+    const double* __restrict__ x, const float* __restrict__ d, const TBase* __restrict__ bases,
+    const double* __restrict__ kinv, int n_poly, double* __restrict__ y,
+    const int32_t* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  __shared__ double red[kMaxTemplates][kTT / 64];
+  __shared__ double scale[kMaxTemplates];
+  __shared__ double coef[kMaxTemplates];
+  const TBase B = bases[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double invL = 1.0 / static_cast<double>(B.len);
+  const double w = static_cast<double>(B.w);
+  if (tid < kMaxTemplates) scale[tid] = sqrt((2.0 * tid + 1.0) * invL);
+  __syncthreads();
+  const int nsteps = (B.len + kStep - 1) / kStep;
+
+  // ---- 1. gather and project ------------------------------------------------------------------
+  double a[kMaxTemplates];
+#pragma unroll
+  for (int k = 0; k < kMaxTemplates; ++k) a[k] = 0.0;
+  int ck[kCached][4];
+  double ct[kCached][4], cq[kCached][4], cu[kCached][4];
+#pragma unroll
+  for (int sidx = 0; sidx < kCached; ++sidx) {
+    if (sidx < nsteps) {
+      const int j0 = sidx * kStep + 4 * tid;
+      load4<kData>(lpix, wq, wu, x, d, B.start, B.len, j0, ck[sidx], ct[sidx], cq[sidx], cu[sidx]);
+      project4(ck[sidx], ct[sidx], j0, invL, w, n_poly, scale, a);
+    }
+  }
+  for (int sidx = kCached; sidx < nsteps; ++sidx) {
+    const int j0 = sidx * kStep + 4 * tid;
+    int k4[4];
+    double t4[4], q4[4], u4[4];
+    load4<kData>(lpix, wq, wu, x, d, B.start, B.len, j0, k4, t4, q4, u4);
+    project4(k4, t4, j0, invL, w, n_poly, scale, a);
+  }
+  // workgroup sums in a fixed order
+#pragma unroll
+  for (int k = 0; k < kMaxTemplates; ++k) {
+    double v = a[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((tid & 63) == 0) red[k][tid >> 6] = v;
+  }
+  __syncthreads();
+
+  // ---- 2. c = K^+ a ---------------------------------------------------------------------------
+  if (tid < kMaxTemplates) {
+    double acc = 0.0;
+    if (tid < n_poly) {
+      const double* K = kinv + static_cast<int64_t>(blockIdx.x) * n_poly * n_poly + tid * n_poly;
+      for (int k = 0; k < n_poly; ++k) {
+        double ak = 0.0;
+        for (int wv = 0; wv < kTT / 64; ++wv) ak += red[k][wv];
+        acc = fma(K[k], ak, acc);
+      }
+    }
+    coef[tid] = acc;
+  }
+  __syncthreads();
+  double c[kMaxTemplates];
+#pragma unroll
+  for (int k = 0; k < kMaxTemplates; ++k) c[k] = coef[k];
+
+  // ---- 3. subtract the fit, weight, point -----------------------------------------------------
+#pragma unroll
+  for (int sidx = 0; sidx < kCached; ++sidx) {
+    if (sidx < nsteps)
+      subtract_point4(ck[sidx], ct[sidx], cq[sidx], cu[sidx], sidx * kStep + 4 * tid, invL, w,
+                      n_poly, scale, c, y);
+  }
+  for (int sidx = kCached; sidx < nsteps; ++sidx) {
+    const int j0 = sidx * kStep + 4 * tid;
+    int k4[4];
+    double t4[4], q4[4], u4[4];
+    load4<kData>(lpix, wq, wu, x, d, B.start, B.len, j0, k4, t4, q4, u4);
+    subtract_point4(k4, t4, q4, u4, j0, invL, w, n_poly, scale, c, y);
+  }
+}
+
+// Kernel blocks K_b = sum_s w_s T_s T_s^T (upper triangle, FP64), one workgroup per baseline.
+__global__ __launch_bounds__(kTT) void k_template_kernel(const int32_t* __restrict__ lpix,
+                                                         const TBase* __restrict__ bases,
+                                                         int n_poly, double* __restrict__ K) {
+  __shared__ double red[kTT / 64];
+  __shared__ double scale[kMaxTemplates];
+  const TBase B = bases[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double invL = 1.0 / static_cast<double>(B.len);
+  if (tid < kMaxTemplates) scale[tid] = sqrt((2.0 * tid + 1.0) * invL);
+  __syncthreads();
+  const double w = static_cast<double>(B.w);
+  for (int i = 0; i < n_poly; ++i) {
+    for (int k = i; k < n_poly; ++k) {
+      double acc = 0.0;
+      for (int j = tid; j < B.len; j += kTT) {
+        if (lpix[B.start + j] < 0) continue;
+        double T[kMaxTemplates];
+        legendre(fma(2.0, static_cast<double>(j), 1.0) * invL - 1.0, n_poly, scale, T);
+        double ti = 0.0, tk = 0.0;
+#pragma unroll
+        for (int m = 0; m < kMaxTemplates; ++m) {
+          if (m == i) ti = T[m];
+          if (m == k) tk = T[m];
+        }
+        acc = fma(w * ti, tk, acc);
+      }
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+      if ((tid & 63) == 0) red[tid >> 6] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        double sum = 0.0;
+        for (int wv = 0; wv < kTT / 64; ++wv) sum += red[wv];
+        K[static_cast<int64_t>(blockIdx.x) * n_poly * n_poly + i * n_poly + k] = sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace
+
+mm_status build_templates(Plan* P, const mm_geometry* g, const std::vector<Tile>& tiles,
+                          hipStream_t s) {
+  const int n_poly = g->n_poly;
+  if (n_poly <= 0) return MM_OK;
+  if (n_poly > kMaxTemplates)
+    return fail(MM_ERR_UNSUPPORTED, "n_poly > " + std::to_string(kMaxTemplates));
+  if (P->lambda_max != 0)
+    return fail(MM_ERR_UNSUPPORTED, "template map-making takes diagonal weights (band_ncoef = 1)");
+  if (g->n_baselines < 0) return fail(MM_ERR_INVALID, "n_baselines < 0");
+  if (g->n_baselines > 0 && (!g->base_start || !g->base_len))
+    return fail(MM_ERR_INVALID, "baseline table pointers are NULL");
+  if (g->n_baselines > INT32_MAX) return fail(MM_ERR_INVALID, "too many baselines");
+  const int64_t nb = g->n_baselines;
+  std::vector<int64_t> order(static_cast<size_t>(nb));
+  for (int64_t i = 0; i < nb; ++i) order[static_cast<size_t>(i)] = i;
+  std::sort(order.begin(), order.end(),
+            [&](int64_t a, int64_t b) { return g->base_start[a] < g->base_start[b]; });
+  // weights: the c_0 of the tile holding the baseline; the baseline must stay inside one block
+  // (or outside all blocks) and, with detector offsets, inside one detector
+  std::vector<int64_t> bstart, bend;  // blocks, sorted by start
+  {
+    std::vector<int> bo(static_cast<size_t>(g->n_blocks));
+    for (int i = 0; i < g->n_blocks; ++i) bo[static_cast<size_t>(i)] = i;
+    std::sort(bo.begin(), bo.end(), [&](int a, int b) { return g->blk_start[a] < g->blk_start[b]; });
+    for (int i : bo) {
+      bstart.push_back(g->blk_start[i]);
+      bend.push_back(g->blk_start[i] + g->blk_len[i]);
+    }
+  }
+  std::vector<TBase> bases;
+  bases.reserve(static_cast<size_t>(nb));
+  int64_t prev_end = 0;
+  for (int64_t i : order) {
+    const int64_t s0 = g->base_start[i], L = g->base_len[i];
+    if (s0 < 0 || L < 1 || s0 + L > g->n_samples)
+      return fail(MM_ERR_INVALID, "baseline " + std::to_string(i) + " outside [0, n_samples)");
+    if (L > INT32_MAX) return fail(MM_ERR_INVALID, "baseline longer than 2^31 samples");
+    if (s0 < prev_end) return fail(MM_ERR_INVALID, "baselines overlap");
+    prev_end = s0 + L;
+    // block containing s0 (last block starting at or before s0)
+    const auto it = std::upper_bound(bstart.begin(), bstart.end(), s0);
+    const int64_t bi = (it - bstart.begin()) - 1;
+    const bool inside = bi >= 0 && s0 < bend[static_cast<size_t>(bi)];
+    if (inside && s0 + L > bend[static_cast<size_t>(bi)])
+      return fail(MM_ERR_INVALID, "baseline " + std::to_string(i) + " crosses a stationary interval");
+    if (!inside) {
+      const int64_t next = bi + 1;
+      if (next < static_cast<int64_t>(bstart.size()) && bstart[static_cast<size_t>(next)] < s0 + L)
+        return fail(MM_ERR_INVALID, "baseline " + std::to_string(i) + " crosses a stationary interval");
+    }
+    if (g->det_offset != nullptr && g->n_dets > 0) {
+      const int64_t* de = g->det_offset;
+      const auto dt = std::upper_bound(de, de + g->n_dets + 1, s0);
+      if (dt == de + g->n_dets + 1 || s0 + L > *dt)
+        return fail(MM_ERR_INVALID, "baseline " + std::to_string(i) + " crosses a detector");
+    }
+    // weight of the covering tile (tiles are sorted and cover [0, n_samples))
+    const auto ti = std::upper_bound(tiles.begin(), tiles.end(), s0,
+                                     [](int64_t v, const Tile& t) { return v < t.start; });
+    const float w = (ti == tiles.begin()) ? 1.0f : (ti - 1)->c0;
+    bases.push_back(TBase{s0, static_cast<int32_t>(L), w});
+  }
+  // samples outside every baseline: the tiles with the baselines cut out
+  std::vector<Tile> free_tiles;
+  {
+    size_t bix = 0;
+    for (const Tile& t : tiles) {
+      int64_t a = t.start;
+      const int64_t e = t.start + t.len;
+      while (a < e) {
+        while (bix < bases.size() && bases[bix].start + bases[bix].len <= a) ++bix;
+        int64_t stop = e;
+        if (bix < bases.size() && bases[bix].start <= a) {
+          a = std::min<int64_t>(e, bases[bix].start + bases[bix].len);  // skip the covered part
+          continue;
+        }
+        if (bix < bases.size()) stop = std::min<int64_t>(e, bases[bix].start);
+        free_tiles.push_back(Tile{a, static_cast<int32_t>(stop - a), t.c0});
+        a = stop;
+      }
+    }
+  }
+  P->n_poly = n_poly;
+  P->n_baselines = nb;
+  MM_TRY(dalloc(P, &P->tbases, bases.size()));
+  MM_TRY(dalloc(P, &P->tkinv, bases.size() * static_cast<size_t>(n_poly * n_poly)));
+  MM_TRY(dalloc(P, &P->free_tiles, free_tiles.size()));
+  P->n_free_tiles = static_cast<int32_t>(free_tiles.size());
+  if (!bases.empty())
+    MM_HIP_TRY(hipMemcpyAsync(P->tbases, bases.data(), bases.size() * sizeof(TBase), hipMemcpyHostToDevice, s));
+  if (!free_tiles.empty())
+    MM_HIP_TRY(hipMemcpyAsync(P->free_tiles, free_tiles.data(), free_tiles.size() * sizeof(Tile),
+                              hipMemcpyHostToDevice, s));
+  if (bases.empty()) {
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    return MM_OK;
+  }
+  // kernel blocks on the device, pseudo-inverses on the host
+  const size_t nk = bases.size() * static_cast<size_t>(n_poly * n_poly);
+  std::vector<double> hk(nk, 0.0);
+  MM_HIP_TRY(hipMemsetAsync(P->tkinv, 0, nk * sizeof(double), s));
+  hipLaunchKernelGGL(k_template_kernel, dim3(static_cast<unsigned>(bases.size())), dim3(kTT), 0, s,
+                     P->lpix, P->tbases, n_poly, P->tkinv);
+  MM_HIP_TRY(hipGetLastError());
+  MM_HIP_TRY(hipMemcpyAsync(hk.data(), P->tkinv, nk * sizeof(double), hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<double> G(static_cast<size_t>(n_poly * n_poly)), Gi;
+  for (size_t b = 0; b < bases.size(); ++b) {
+    double* Kb = hk.data() + b * n_poly * n_poly;
+    for (int i = 0; i < n_poly; ++i)
+      for (int k = 0; k < n_poly; ++k)
+        G[static_cast<size_t>(i * n_poly + k)] = i <= k ? Kb[i * n_poly + k] : Kb[k * n_poly + i];
+    bool zero = true;
+    for (double v : G) zero = zero && v == 0.0;
+    if (zero) {
+      std::fill(Kb, Kb + n_poly * n_poly, 0.0);
+      continue;
+    }
+    sym_pinv(G, n_poly, 1e-12, Gi);
+    std::copy(Gi.begin(), Gi.end(), Kb);
+  }
+  MM_HIP_TRY(hipMemcpyAsync(P->tkinv, hk.data(), nk * sizeof(double), hipMemcpyHostToDevice, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  return MM_OK;
+}
+
+mm_status launch_template_apply(Plan* P, const double* x, const float* d, double* y,
+                                const int32_t* done, hipStream_t s) {
+  TimedLaunch tl(P, K_TOEPLITZ, s);
+  if (P->n_baselines > 0) {
+    if (x != nullptr)
+      hipLaunchKernelGGL(k_template_apply<false>, dim3(static_cast<unsigned>(P->n_baselines)),
+                         dim3(kTT), 0, s, P->lpix, P->wq, P->wu, x, d, P->tbases, P->tkinv,
+                         P->n_poly, y, done);
+    else
+      hipLaunchKernelGGL(k_template_apply<true>, dim3(static_cast<unsigned>(P->n_baselines)),
+                         dim3(kTT), 0, s, P->lpix, P->wq, P->wu, x, d, P->tbases, P->tkinv,
+                         P->n_poly, y, done);
+    MM_HIP_TRY(hipGetLastError());
+  }
+  if (P->n_free_tiles > 0)
+    MM_TRY(launch_diag_tiles(P, P->free_tiles, P->n_free_tiles, x, d, y, done, s));
+  return MM_OK;
+}
+
+}  // namespace mm
