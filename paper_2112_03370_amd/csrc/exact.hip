@@ -180,6 +180,25 @@ __global__ __launch_bounds__(kXThreads) void k_x_pass(const double2* __restrict_
 }
 
 // ---- real spectrum times the band symbol, repacked and conjugated -----------------------
+// From Z[k] and Z[NC - k] of the packed forward transform: even / odd half spectra
+// E = (Z[k] + conj Z[-k]) / 2, O = (Z[k] - conj Z[-k]) / (2i), X[k] = E + W_N^k O and
+// X[NC - k] = conj(E - W_N^k O); Y = S X; the half-length inverse takes
+// Q[k] = (Y[k] + Y[k + NC]) + i (Y[k] - Y[k + NC]) conj(W_N^k) with Y[k + NC] = conj Y[NC - k];
+// returned conjugated, so that a forward transform inverts it.
+__device__ __forceinline__ double2 spectrum_q(double2 zk, double2 zm, double2 w, double sk,
+                                              double sm) {
+  const double2 e = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+  const double2 od = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
+  const double2 wo = cmul(w, od);
+  const double2 xk = cadd(e, wo);           // X[k]
+  const double2 xm = cconj(csub(e, wo));    // X[NC - k] (X[NC] for k = 0)
+  const double2 yk = make_double2(sk * xk.x, sk * xk.y);
+  const double2 ymc = make_double2(sm * xm.x, -sm * xm.y);  // conj Y[NC - k]
+  const double2 fe = cadd(yk, ymc);
+  const double2 fo = cmul(csub(yk, ymc), cconj(w));
+  return make_double2(fe.x - fo.y, -(fe.y + fo.x));
+}
+
 __global__ __launch_bounds__(kXThreads) void k_x_spectrum(
     const double2* __restrict__ Z, double2* __restrict__ out, const double2* __restrict__ tw,
     const double* __restrict__ spec, const Chunk* __restrict__ chunks, int seg0, int NC) {
@@ -187,23 +206,7 @@ __global__ __launch_bounds__(kXThreads) void k_x_spectrum(
   if (k >= NC) return;
   const int64_t base = static_cast<int64_t>(blockIdx.y) * NC;
   const double* S = spec + static_cast<int64_t>(chunks[seg0 + blockIdx.y].band) * (NC + 1);
-  const double2 zk = Z[base + k];
-  const double2 zm = Z[base + ((NC - k) & (NC - 1))];
-  // even / odd half spectra: E = (Z[k] + conj Z[-k]) / 2, O = (Z[k] - conj Z[-k]) / (2i)
-  const double2 e = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
-  const double2 od = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
-  const double2 w = tw[k];  // W_N^k
-  const double2 wo = cmul(w, od);
-  const double2 xk = cadd(e, wo);           // X[k]
-  const double2 xm = cconj(csub(e, wo));    // X[NC - k] (X[NC] for k = 0)
-  const double2 yk = make_double2(S[k] * xk.x, S[k] * xk.y);
-  const double2 ym = make_double2(S[NC - k] * xm.x, S[NC - k] * xm.y);
-  // Q = (Y[k] + Y[k + NC]) + i (Y[k] - Y[k + NC]) conj(W_N^k), Y[k + NC] = conj Y[NC - k]
-  const double2 ymc = cconj(ym);
-  const double2 fe = cadd(yk, ymc);
-  const double2 fo = cmul(csub(yk, ymc), cconj(w));
-  const double2 q = make_double2(fe.x - fo.y, fe.y + fo.x);
-  out[base + k] = cconj(q);
+  out[base + k] = spectrum_q(Z[base + k], Z[base + ((NC - k) & (NC - 1))], tw[k], S[k], S[NC - k]);
 }
 
 struct XFlush {
@@ -306,6 +309,297 @@ __global__ __launch_bounds__(kXThreads) void k_x_direct(
   }
 }
 
+// ---- one segment per workgroup: FP64 transform with the data in registers ----------------
+// NC = 2^M complex points (M = 11..14), T = NC / 16 threads of 16 points each.  Stockham passes
+// of radix 16, then (8 or) 4, then a last radix-4 pass; between passes the points move through
+// LDS one component at a time (NC doubles, padded one per 16 against bank conflicts).  Pass
+// butterflies b = t + i T (i < 16 / R); the last pass of the forward transform instead gives
+// thread t the butterflies {t, 4T - t, t + T, 3T - t} (thread 0: {0, 2T, T, 3T}), so that every
+// output k = b + m NC / 4 finds its mirror NC - k in the same thread and the real-spectrum step
+// runs in registers.
+template <int M>
+struct XFused {
+  static constexpr int NC = 1 << M;
+  static constexpr int T = NC / 16;
+  static constexpr int R2 = M == 11 ? 8 : 16;            // second pass
+  static constexpr int R3 = M == 11 ? 4 : (M == 12 ? 4 : (M == 13 ? 8 : 16));
+  static constexpr int LDS = NC + NC / 16;  // exchange area (32 more doubles: thread 0's slot)
+};
+
+__device__ __forceinline__ int xpad(int i) { return i + (i >> 4); }
+
+// Butterfly i of thread t in a radix-R pass (16 / R per thread).
+template <int R, int T>
+__device__ __forceinline__ int xbutterfly(int t, int i, bool paired) {
+  if (paired) {  // R == 4: {t, 4T - t, t + T, 3T - t}, thread 0 {0, 2T, T, 3T}
+    if (i == 0) return t;
+    if (i == 1) return t == 0 ? 2 * T : 4 * T - t;
+    if (i == 2) return t + T;
+    return 3 * T - t;
+  }
+  return t + i * T;
+}
+
+// Input slot s = i R + j of a radix-R pass: point b_i + j NC / R.
+template <int R, int T>
+__device__ __forceinline__ int xin_pos(int t, int s, bool paired) {
+  constexpr int NB = 16 * T / R;
+  return xbutterfly<R, T>(t, s / R, paired) + (s % R) * NB;
+}
+
+// Output slot s = i R + m of a radix-R pass after p points were transformed: (b - k) R + k + m p.
+template <int R, int T>
+__device__ __forceinline__ int xout_pos(int t, int s, int p, bool paired) {
+  const int b = xbutterfly<R, T>(t, s / R, paired);
+  const int k = b & (p - 1);
+  return (b - k) * R + k + (s % R) * p;
+}
+
+// An opaque copy of a value: the compiler cannot prove it equal to the original, so addresses
+// and table loads of the two transforms are not merged and kept live across both (the second
+// transform recomputes them instead of holding the first one's in registers).
+template <class V>
+__device__ __forceinline__ V xopaque(V v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// One radix-R pass on the registers (inputs already in place).
+template <int R, int T>
+__device__ __forceinline__ void xpass(double2 (&v)[16], int t, int p, bool paired,
+                                      const double2* __restrict__ tw) {
+  constexpr int NC = 16 * T;
+#pragma unroll
+  for (int i = 0; i < 16 / R; ++i) {
+    const int b = xbutterfly<R, T>(t, i, paired);
+    const int k = b & (p - 1);
+    double2(&u)[R] = *reinterpret_cast<double2(*)[R]>(v + i * R);
+    if (p > 1) {
+      // W_(pR)^(j k) from the table for j = 1, 2, 4, 8 and by products for the others
+      const int step = 2 * k * (NC / (p * R));
+      const double2 w1 = tw_n(tw, step, NC);
+      double2 w2 = make_double2(1.0, 0.0), w4 = w2, w8 = w2;
+      if (R > 2) w2 = tw_n(tw, 2 * step, NC);
+      if (R > 4) w4 = tw_n(tw, 4 * step, NC);
+      if (R > 8) w8 = tw_n(tw, 8 * step, NC);
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        double2 w = (j & 1) ? w1 : make_double2(1.0, 0.0);
+        if (j & 2) w = (j & 1) ? cmul(w, w2) : w2;
+        if (j & 4) w = (j & 3) ? cmul(w, w4) : w4;
+        if (j & 8) w = (j & 7) ? cmul(w, w8) : w8;
+        u[j] = cmul(u[j], w);
+      }
+    }
+    dft<R>(u);
+    __builtin_amdgcn_sched_barrier(0);  // one butterfly's twiddles in flight at a time
+  }
+}
+
+// Move the points from the output slots of pass A to the input slots of pass B through LDS.
+template <int RA, int RB, int T>
+__device__ __forceinline__ void xexchange(double2 (&v)[16], double* sh, int t, int pa,
+                                          bool paired_a, bool paired_b) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int tw_ = xopaque(t);  // addresses recomputed per component, not held across
+#pragma unroll
+    for (int s = 0; s < 16; ++s) sh[xpad(xout_pos<RA, T>(tw_, s, pa, paired_a))] = c ? v[s].y : v[s].x;
+    __syncthreads();
+    const int tr_ = xopaque(t);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const double val = sh[xpad(xin_pos<RB, T>(tr_, s, paired_b))];
+      if (c) v[s].y = val; else v[s].x = val;
+    }
+    __syncthreads();
+  }
+}
+
+// Forward transform: inputs at the first pass's slots, outputs at the last pass's slots.
+template <int M>
+__device__ __forceinline__ void xfft(double2 (&v)[16], double* sh, int t, bool paired_last,
+                                     const double2* __restrict__ tw) {
+  using C = XFused<M>;
+  constexpr int T = C::T, R2 = C::R2, R3 = C::R3;
+  xpass<16, T>(v, t, 1, false, tw);
+  xexchange<16, R2, T>(v, sh, t, 1, false, false);
+  xpass<R2, T>(v, t, 16, false, tw);
+  xexchange<R2, R3, T>(v, sh, t, 16, false, false);
+  xpass<R3, T>(v, t, 16 * R2, false, tw);
+  xexchange<R3, 4, T>(v, sh, t, 16 * R2, false, paired_last);
+  xpass<4, T>(v, t, 16 * R2 * R3, paired_last, tw);
+}
+
+template <int M, bool kData>
+__global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
+    const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
+    const double* __restrict__ x, const float* __restrict__ d, const Chunk* __restrict__ chunks,
+    int lam, const double* __restrict__ spec, const double2* __restrict__ tw0, double inv_n,
+    double* __restrict__ y) {
+  using C = XFused<M>;
+  constexpr int NC = C::NC, T = C::T, PL = NC / 4;
+  static_assert(C::R2 * C::R3 * 16 * 4 == NC, "pass radices");
+  __shared__ double sh[C::LDS + 32];
+  const Chunk c = chunks[blockIdx.x];
+  const int t = threadIdx.x;
+  const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
+
+  // ---- window samples, packed as complex points at the first pass's slots ------------------
+  // staged through LDS one component at a time (even samples, then odd ones): a plain loop
+  // keeps the gather's loads from all being in flight at once
+  double2 v[16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int n = t; n < NC; n += T) {
+      const int64_t g = c.out0 - lam + 2 * static_cast<int64_t>(n) + h;
+      double val = 0.0;
+      if (g >= b0 && g < b1) {
+        const int p = lpix[g];
+        if (p >= 0) {
+          if (kData) {
+            val = static_cast<double>(d[g]);
+          } else {
+            const double* m = x + 3 * static_cast<int64_t>(p);
+            val = m[0] + static_cast<double>(wq[g]) * m[1] + static_cast<double>(wu[g]) * m[2];
+          }
+        }
+      }
+      sh[xpad(n)] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double val = sh[xpad(t + j * T)];
+      if (h) v[j].y = val; else v[j].x = val;
+    }
+    __syncthreads();
+  }
+
+  // ---- forward transform; real spectrum x symbol with mirrors in the same thread -----------
+  xfft<M>(v, sh, t, true, tw0);
+  {
+    const int t = xopaque(threadIdx.x);
+    const double2* __restrict__ tw = reinterpret_cast<const double2*>(
+        xopaque(reinterpret_cast<uintptr_t>(tw0)));
+    // slot s = 4 i + m holds point k = b_i + m PL; its mirror NC - k is in the same thread:
+    // slots (8 + m, 15 - m) always, (m, 7 - m) for t > 0; thread 0 holds k = 0 and NC/2 alone
+    // (slots 0 and 2) and pairs (1, 3), (4, 7), (5, 6)
+    const double* S = spec + static_cast<int64_t>(c.band) * (NC + 1);
+    auto kpos = [&](int s) {
+      return xbutterfly<4, T>(xopaque(t), s >> 2, true) + (s & 3) * PL;
+    };
+    auto pair = [&](int a, int b) {
+      const int ka = kpos(a), kb = NC - ka;
+      const double2 za = v[a], zb = v[b];
+      const double sa = S[ka], sb = S[kb];
+      v[a] = spectrum_q(za, zb, tw_n(tw, ka, NC), sa, sb);
+      v[b] = spectrum_q(zb, za, tw_n(tw, kb, NC), sb, sa);
+      __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight (register pressure)
+    };
+    // Thread 0's first two butterflies (0 and 2T) pair within themselves: it parks their
+    // points in a private LDS slot, runs the common pairing with everyone (its slots 0..7 come
+    // out wrong there), lanes 0..7 of its wavefront redo one of those slots each from the
+    // parked points, and thread 0 reloads them.
+    double2* own = reinterpret_cast<double2*>(sh + C::LDS);  // [0, 8) parked, [8, 16) redone
+    if (t == 0) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) own[s2] = v[s2];
+    }
+    wave_lds_sync();
+    // one half of the points at a time in registers, the other parked in the (idle) exchange
+    // area at lane-consecutive addresses
+    auto park = [&](int base) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        sh[(2 * s2) * T + t] = v[base + s2].x;
+        sh[(2 * s2 + 1) * T + t] = v[base + s2].y;
+      }
+    };
+    auto unpark = [&](int base) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2)
+        v[base + s2] = make_double2(sh[(2 * s2) * T + t], sh[(2 * s2 + 1) * T + t]);
+    };
+    park(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pair(8 + m, 15 - m);
+    __builtin_amdgcn_sched_barrier(0);
+    unpark(0);
+    park(8);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pair(m, 7 - m);
+    __builtin_amdgcn_sched_barrier(0);
+    unpark(8);
+    if (t < 8) {
+      // slot t of thread 0: butterfly 0 holds k = t PL (mirror slot (4 - t) mod 4), butterfly
+      // 2T holds k = 2T + (t - 4) PL (mirror slot 11 - t)
+      const int mir = t < 4 ? ((4 - t) & 3) : 11 - t;
+      const int k = t < 4 ? t * PL : 2 * T + (t - 4) * PL;
+      own[8 + t] = spectrum_q(own[t], own[mir], tw_n(tw, k, NC), S[k], S[NC - k]);
+    }
+    wave_lds_sync();
+    if (t == 0) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) v[s2] = own[8 + s2];
+    }
+  }
+  // back to the first pass's slots, then the forward transform of conj Q
+  __syncthreads();  // every thread has reloaded its parked points
+  {
+    const int t2 = xopaque(threadIdx.x);
+    const double2* __restrict__ tw2 = reinterpret_cast<const double2*>(
+        xopaque(reinterpret_cast<uintptr_t>(tw0)));
+    xexchange<4, 16, T>(v, sh, t2, PL, true, false);
+    xfft<M>(v, sh, t2, false, tw2);
+  }
+
+  // ---- outputs y[n] = Re G[n/2] / N (n even), -Im G[n/2] / N (n odd), staged in LDS -------
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k = xbutterfly<4, T>(t, s >> 2, false) + (s & 3) * PL;
+    const int o0 = 2 * k - lam;
+    if (o0 >= 0 && o0 < c.out_len) sh[xpad(o0)] = v[s].x * inv_n;
+    if (o0 + 1 >= 0 && o0 + 1 < c.out_len) sh[xpad(o0 + 1)] = -v[s].y * inv_n;
+  }
+  __syncthreads();
+  for (int o0 = 4 * t; o0 - 4 * t < c.out_len; o0 += 4 * T) {
+    int key[4];
+    double vv[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = o0 + i;
+      key[i] = -1;
+      vv[i][0] = vv[i][1] = vv[i][2] = 0.0;
+      if (o < c.out_len) {
+        const int64_t g = c.out0 + o;
+        const int p = lpix[g];
+        if (p >= 0) {
+          const double u = sh[xpad(o)];
+          key[i] = p;
+          vv[i][0] = u;
+          vv[i][1] = static_cast<double>(wq[g]) * u;
+          vv[i][2] = static_cast<double>(wu[g]) * u;
+        }
+      }
+    }
+    wave_merge_runs<3>(key, vv, XFlush{y});
+  }
+}
+
+template <int M>
+mm_status launch_fused_m(Plan* P, const double* x, const float* d, double* y, hipStream_t s) {
+  const double inv_n = 1.0 / static_cast<double>(P->fft_n);
+  if (x == nullptr)
+    hipLaunchKernelGGL((k_x_fused<M, true>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s, P->lpix,
+                       P->wq, P->wu, x, d, P->chunks, P->lambda_max, P->x_spec, P->x_tw, inv_n, y);
+  else
+    hipLaunchKernelGGL((k_x_fused<M, false>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s, P->lpix,
+                       P->wq, P->wu, x, d, P->chunks, P->lambda_max, P->x_spec, P->x_tw, inv_n, y);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
 // Device buffer released at scope exit (after the caller's stream has been synchronised).
 template <class T>
 struct XBuf {
@@ -385,6 +679,19 @@ mm_status exact_product(Plan* P, const double* x, const float* d, double* y, hip
   const bool data = x == nullptr;
   if (P->n_poly > 0) return launch_template_apply(P, x, d, y, nullptr, s);  // FP64 already
   if (P->lambda_max == 0) return launch_diag_apply(P, x, d, y, nullptr, s);
+  if (P->algo == MM_TOEPLITZ_FFT && P->n_chunks > 0 && P->fft_n >= (1 << 12) &&
+      P->fft_n <= (1 << 15) && P->fft_n - 2 * P->lambda_max <= P->fft_n / 2) {
+    // one workgroup per segment with the transform in registers and LDS
+    MM_TRY(prepare(P, s));
+    switch (P->fft_n) {
+      case 1 << 12: MM_TRY(launch_fused_m<11>(P, x, d, y, s)); break;
+      case 1 << 13: MM_TRY(launch_fused_m<12>(P, x, d, y, s)); break;
+      case 1 << 14: MM_TRY(launch_fused_m<13>(P, x, d, y, s)); break;
+      default: MM_TRY(launch_fused_m<14>(P, x, d, y, s)); break;
+    }
+    if (P->n_id_tiles > 0) MM_TRY(launch_diag_tiles(P, P->id_tiles, P->n_id_tiles, x, d, y, nullptr, s));
+    return MM_OK;
+  }
   if (P->algo == MM_TOEPLITZ_FFT) {
     MM_TRY(prepare(P, s));
     const int N = P->fft_n, NC = N / 2;

@@ -10,9 +10,13 @@ the host cores) inside a couple of minutes per case.
 
 Checks, with tolerances derived from the arithmetic:
   * kept pixel ids and hit counts: bit-exact;
-  * the GPU map at recursive 1e-8 against the oracle's FP64 map at 1e-8: relative L2 <= 1e-6
-    (FP32 time-domain floor ~1e-7 to 3e-7, measured by the oracle's emulation), iteration
-    counts within 2;
+  * the refined GPU map (FP64 true residual < 1e-8, the standard the oracle's map meets with its
+    recursive 1e-8) against the oracle's FP64 map at 1e-8: relative L2 <= 1e-6; two maps with
+    FP64 residuals <= 1e-8 differ by at most 2 kappa_eff 1e-8, and kappa_eff (map error over
+    residual) is ~16 on the 16-detector ground slice (143 iterations);
+  * the plain GPU map (recursive 1e-8, FP64 true residual ~6e-8: the FP32 product floor)
+    against the same oracle map: relative L2 <= 3e-6, the same bound with its ~6x larger
+    residual; iteration counts within 2;
   * the GPU map's FP64 true residual ||b - A x|| / ||b|| recomputed by the oracle: below 2e-7
     (the FP32 product floor, ~5e-8 measured), and equal to the library's own FP64 exit check to
     1e-4 relative;
@@ -58,6 +62,9 @@ def test_workload_slice_map_parity(gpu_lib, name, n_dets):
     assert r_ref < 1e-8 and info_r["converged"] == 1
     res = O.pcg(ref, b, tol=1e-8)
     err = np.linalg.norm(m - res.x) / np.linalg.norm(res.x)
-    print(f"[{name}] oracle: {res.iterations} iterations; map rel L2 {err:.2e}", flush=True)
+    err_r = np.linalg.norm(mr - res.x) / np.linalg.norm(res.x)
+    print(f"[{name}] oracle: {res.iterations} iterations; map rel L2 plain {err:.2e}, "
+          f"refined {err_r:.2e}", flush=True)
     assert res.converged and abs(info["iterations"] - res.iterations) <= 2
-    assert err <= 1e-6
+    assert err_r <= 1e-6
+    assert err <= 3e-6

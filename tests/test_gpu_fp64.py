@@ -59,6 +59,17 @@ CASES = {
                                            interval=1 << 16, side=32, lam=8192), {}),
     "fft_2e17": (lambda: synth.make_ground(cfg_id=96, n_dets=2, samples_per_det=1 << 18,
                                            interval=3 << 16, side=32, lam=20000), {}),
+    # one workgroup per segment with the FP64 transform in registers (N = 2^12 .. 2^15, at most
+    # N/2 outputs per segment): odd lambda, ragged intervals, flags
+    "fused_2e12": (lambda: synth.make_ground(cfg_id=97, n_dets=3, samples_per_det=30011,
+                                             interval=10007, side=24, lam=1025,
+                                             flag_frac=0.02), {"fft_size": 1 << 12}),
+    "fused_2e13": (lambda: synth.make_ground(cfg_id=98, n_dets=2, samples_per_det=40009,
+                                             interval=20011, side=24, lam=2048,
+                                             flag_frac=0.01), {}),
+    "fused_2e14": (lambda: synth.make_ground(cfg_id=99, n_dets=2, samples_per_det=70001,
+                                             interval=30011, side=24, lam=4097),
+                   {"fft_size": 1 << 14}),
 }
 
 _cache = {}
@@ -86,7 +97,7 @@ def test_fp64_product_elementwise(gpu_lib, name):
     assert np.linalg.norm(b - bw) / np.linalg.norm(bw) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["direct_lam24", "fft_2e13", "fft_2e15"])
+@pytest.mark.parametrize("name", ["direct_lam24", "fft_2e13", "fft_2e15", "fused_2e12"])
 def test_fp64_plan_pcg_matches_oracle(gpu_lib, name):
     prob, ref, kw = case(name)
     plan = gpu_lib.Plan.from_problem(prob, precision=gpu_lib.PRECISION_FP64, **kw)
@@ -112,7 +123,7 @@ def test_fp64_exit_check_matches_oracle_residual(gpu_lib, name):
           f"FP64 true {info['true_relres64']:.2e} (oracle {r:.2e})", flush=True)
 
 
-@pytest.mark.parametrize("name", ["fft_2e13", "fft_2e15", "fft_2e17"])
+@pytest.mark.parametrize("name", ["fft_2e13", "fft_2e15", "fft_2e17", "fused_2e14"])
 def test_refinement_reaches_fp64_tolerance(gpu_lib, name):
     prob, ref, kw = case(name)
     plan = gpu_lib.Plan.from_problem(prob, **kw)  # mixed precision
