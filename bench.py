@@ -41,6 +41,9 @@ WORKLOADS = {
     "serving": "serving: 400 requests, Poisson arrivals at 0.8x the sequential capacity, Zipf(1.1) "
                "over 24 ground-like geometries (4-32 det x 2^16-2^18 samples, 32^2-128^2 patches, "
                "lambda 2^8-2^13), 1-4 RHS per request",
+    "templates": "template map-making: ground-like 256 det x 2^20 samples (268,435,456), white "
+                 "noise with per-detector sigma (diagonal weights), Legendre baselines of degree "
+                 "< 3 on every 8,192-sample sweep, polynomial drifts in the data",
 }
 
 
@@ -102,7 +105,20 @@ def make_workload(name):
         return synth.make_config("satellite")
     if name == "batched":
         return synth.make_config("batched")
+    if name == "templates":
+        return synth.make_templates(cfg_id=5, n_dets=256, samples_per_det=1 << 20,
+                                    interval=1 << 16, side=512, dwell=16, baseline=8192,
+                                    n_poly=3, name="templates")
     raise SystemExit(f"unknown workload {name}")
+
+
+def plan_kwargs(args, prob):
+    """Plan arguments beyond the geometry: flags, and the baselines of template workloads."""
+    kw = {"flags": plan_flags(args)}
+    if prob.meta.get("kind") == "templates":
+        kw.update(n_poly=prob.meta["n_poly"], base_start=prob.meta["base_start"],
+                  base_len=prob.meta["base_len"])
+    return kw
 
 
 def cpu_baseline(prob, target_s=15.0):
@@ -118,13 +134,21 @@ def cpu_baseline(prob, target_s=15.0):
     sel = prob.blk_start + prob.blk_len <= s1
     plan = O.build_plan(prob.pix[:s1], prob.wq[:s1], prob.wu[:s1], prob.n_pix_global,
                         prob.blk_start[sel], prob.blk_len[sel], prob.blk_band[sel], prob.bands)
-    b = O.rhs(plan, prob.d[0, :s1])
+    apply = None
+    if prob.meta.get("kind") == "templates":
+        bs, bl = prob.meta["base_start"], prob.meta["base_len"]
+        keep = bs + bl <= s1
+        tp = O.build_template_plan(plan, bs[keep], bl[keep], prob.meta["n_poly"])
+        b = O.template_rhs(tp, prob.d[0, :s1])
+        apply = lambda v: O.template_apply_A(tp, v)  # noqa: E731
+    else:
+        b = O.rhs(plan, prob.d[0, :s1])
     t0 = time.perf_counter()
-    res = O.pcg(plan, b, tol=1e-30, max_iter=1)
+    res = O.pcg(plan, b, tol=1e-30, max_iter=1, apply=apply)
     one = time.perf_counter() - t0
     iters = int(max(1, min(50, target_s // max(one, 1e-3))))
     t0 = time.perf_counter()
-    res = O.pcg(plan, b, tol=1e-30, max_iter=iters)
+    res = O.pcg(plan, b, tol=1e-30, max_iter=iters, apply=apply)
     dt = time.perf_counter() - t0
     # pcg performs one extra product for the true residual: iters + 1 products were timed
     rate = s1 * (iters + 1) / dt
@@ -482,6 +506,152 @@ def run_serving(args, mm, torch, dev):
     }
 
 
+def run_plain(args, prob, name, mm, torch, dev, steps, warmup, refine):
+    """One solve per step (plan, b, PCG to recursive 1e-8, FP64 refinement when refine > 0,
+    release) on one workload; TOD samples x CG iterations per second, with the dominant kernel's
+    roofline and the oracle's rate on the host."""
+    pix = torch.from_numpy(prob.pix).to(dev)
+    wq = torch.from_numpy(prob.wq).to(dev)
+    wu = torch.from_numpy(prob.wu).to(dev)
+    d = torch.from_numpy(prob.d[0]).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    kw = plan_kwargs(args, prob)
+    phases = []
+
+    def step(timing=False, refine_steps=refine):
+        with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
+            plan = mm.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                           prob.blk_band, prob.bands, det_offset=prob.det_offset, stream=stream,
+                           **kw)
+            t1 = time.perf_counter()
+            if timing:
+                plan.set_timing(True)
+            x, info = plan.pcg_solve(d, tol=args.tol, refine=refine_steps, stream=stream)
+            t2 = time.perf_counter()
+            kt = None
+            if timing:
+                kt = {k: plan.kernel_time(k) for k in range(4)}
+            pinfo = plan.info
+            plan.close()
+            t3 = time.perf_counter()
+        phases.append((t1 - t0, t2 - t1, t3 - t2))
+        return x, info, pinfo, kt
+
+    for w in range(warmup):
+        _, info, pinfo, _ = step()
+        log(f"[bench] {name} warmup {w}: {info['iterations']} + {info['inner_iterations']} "
+            f"iterations, {info['ms']:.1f} ms solve")
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = []
+    kts = []
+    for k in range(steps):
+        x, info, pinfo, kt = step(timing=True)
+        infos.append(info)
+        kts.append(kt)
+        log(f"[bench] {name} step {k}: {info['iterations']} + {info['inner_iterations']} it, "
+            f"relres {info['relres']:.2e}, FP32-product true {info['true_relres']:.2e}, FP64 true "
+            f"{info['true_relres64']:.2e}, solve {info['ms']:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1e3 * elapsed / steps
+    iters = float(np.mean([i["iterations"] + i["inner_iterations"] for i in infos]))
+    value = prob.n_samples * iters / (elapsed / steps)
+
+    # the same solve without refinement (outside the timed region): recursive residual only
+    plain = None
+    if refine > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, pi, _, _ = step(refine_steps=0)
+        torch.cuda.synchronize()
+        plain = {"ms_per_step": round(1e3 * (time.perf_counter() - t0), 3),
+                 "iterations": pi["iterations"], "relres": pi["relres"],
+                 "value": prob.n_samples * pi["iterations"] / (time.perf_counter() - t0)}
+
+    # Dominant kernel and its roofline.
+    n_s = prob.n_samples
+    tot = {k: sum(kt[k][0] for kt in kts) for k in range(4)}
+    cnt = {k: sum(kt[k][1] for kt in kts) for k in range(4)}
+    fused = bool(pinfo["fused"])
+    templates = pinfo["n_poly"] > 0
+    toep = "toeplitz_long" if pinfo["fft_size"] > (1 << 15) else "toeplitz"
+    names = {0: "unpoint", 1: "template_apply" if templates else (fused_kernel(pinfo) if fused else toep),
+             2: "point", 3: "cg_vector"}
+    dom = max(range(3), key=lambda k: tot[k])
+    avg_ms = tot[dom] / max(1, cnt[dom])
+    # algorithmic bytes per sample and launch (one launch covers n_samples): pointing is 12 B
+    # (pixel int32 + two FP32 weights); time-domain vectors 4 B each
+    if dom == 1 and (fused or templates):
+        bytes_per_sample = 12                 # pointing read once; t and u stay on chip
+    else:
+        bytes_per_sample = {0: 12 + 4, 1: 4 + 4, 2: 12 + 4}[dom]
+    algo_bytes = bytes_per_sample * n_s
+    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = committed_traffic(names[dom], name) if names[dom] in KERNEL_SOURCES else None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": names[dom], "avg_launch_ms": round(avg_ms, 4),
+            "bytes_per_launch": algo_bytes}
+    if dom == 1 and not templates and pinfo["toeplitz_algo"] == mm.TOEPLITZ_FFT:
+        flops = n_s * fft_flops_per_sample(pinfo)
+        roof["fp32_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
+        roof["fp32_frac"] = round(flops / (avg_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)
+    per_kernel = {names[k]: {"total_ms": round(tot[k], 2), "launches": cnt[k],
+                             "avg_ms": round(tot[k] / max(1, cnt[k]), 4)} for k in range(4)}
+    log(f"[bench] {name} per-kernel (timed steps): {json.dumps(per_kernel)}")
+    ph = np.mean(np.array(phases[warmup:warmup + steps]), axis=0) * 1e3
+    log(f"[bench] {name} step phases (ms): plan {ph[0]:.1f}, solve {ph[1]:.1f}, "
+        f"release {ph[2]:.1f}")
+
+    if args.copy_probe_gib > 0:
+        nbytes = int(args.copy_probe_gib * (1 << 30))
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {nbytes} bytes read + {nbytes} bytes written per launch")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        cpu = cpu_baseline(prob)
+        log(f"[bench] {name} cpu baseline {cpu['value']:.3e} in {time.time() - t0:.1f} s")
+
+    last = infos[-1]
+    return {
+        "metric": "TOD samples x CG iters/s at rel-res 1e-8",
+        "value": value,
+        "unit": "TOD samples x CG iters/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 time-domain / f64 pixel-domain" if not templates else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[name], "n_samples": n_s,
+                   "iterations": int(last["iterations"]),
+                   "refine_iterations": int(last["inner_iterations"]),
+                   "refine_steps": int(last["refine_steps"]), "tol": args.tol,
+                   "relres_recursive": last["relres"],
+                   "true_relres64": max(i["true_relres64"] for i in infos),
+                   "n_kept": pinfo["n_kept"], "fft_size": pinfo["fft_size"],
+                   "n_poly": pinfo["n_poly"], "parallelism": "single GPU"},
+        "unrefined": plain,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
+def free_host():
+    """Release the host arrays of a workload the caller has dropped."""
+    import gc
+    gc.collect()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -489,6 +659,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="ground", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--refine", type=int, default=1,
+                    help="FP64 refinement steps after each solve (0: recursive residual only)")
+    ap.add_argument("--no-suite", action="store_true",
+                    help="ground workload only: skip the satellite, template, batched and "
+                         "serving sub-records")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lds-fft", action="store_true",
                     help="keep 2^15-sample segments in the LDS-resident fused kernel")
@@ -526,117 +701,34 @@ def main():
         stream = torch.cuda.Stream(device=dev)
         print(json.dumps(run_batched(args, prob, mm, torch, dev, stream)), flush=True)
         return
-    pix = torch.from_numpy(prob.pix).to(dev)
-    wq = torch.from_numpy(prob.wq).to(dev)
-    wu = torch.from_numpy(prob.wu).to(dev)
-    d = torch.from_numpy(prob.d[0]).to(dev)
-    stream = torch.cuda.Stream(device=dev)
-    torch.cuda.synchronize()
+    out = run_plain(args, prob, args.config, mm, torch, dev, args.steps, args.warmup, args.refine)
+    del prob
+    free_host()
+    torch.cuda.empty_cache()
 
-    phases = []
-
-    def step(timing=False):
-        with torch.cuda.stream(stream):
-            t0 = time.perf_counter()
-            plan = mm.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
-                           prob.blk_band, prob.bands, det_offset=prob.det_offset,
-                           flags=plan_flags(args), stream=stream)
-            t1 = time.perf_counter()
-            if timing:
-                plan.set_timing(True)
-            x, info = plan.pcg_solve(d, tol=args.tol, stream=stream)
-            t2 = time.perf_counter()
-            kt = None
-            if timing:
-                kt = {k: plan.kernel_time(k) for k in range(4)}
-            pinfo = plan.info
-            plan.close()
-            t3 = time.perf_counter()
-        phases.append((t1 - t0, t2 - t1, t3 - t2))
-        return x, info, pinfo, kt
-
-    for w in range(args.warmup):
-        _, info, pinfo, _ = step()
-        log(f"[bench] warmup {w}: {info['iterations']} iterations, {info['ms']:.1f} ms solve")
-
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    infos = []
-    kts = []
-    for k in range(args.steps):
-        x, info, pinfo, kt = step(timing=True)
-        infos.append(info)
-        kts.append(kt)
-        log(f"[bench] step {k}: {info['iterations']} it, relres {info['relres']:.2e}, "
-            f"true {info['true_relres']:.2e}, solve {info['ms']:.1f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_step = 1e3 * elapsed / args.steps
-    iters = int(np.mean([i["iterations"] for i in infos]))
-    value = prob.n_samples * iters / (elapsed / args.steps)
-
-    # Dominant kernel and its roofline.
-    n_s = prob.n_samples
-    tot = {k: sum(kt[k][0] for kt in kts) for k in range(4)}
-    cnt = {k: sum(kt[k][1] for kt in kts) for k in range(4)}
-    fused = bool(pinfo["fused"])
-    toep = "toeplitz_long" if pinfo["fft_size"] > (1 << 15) else "toeplitz"
-    names = {0: "unpoint", 1: fused_kernel(pinfo) if fused else toep, 2: "point", 3: "cg_vector"}
-    dom = max(range(3), key=lambda k: tot[k])
-    avg_ms = tot[dom] / max(1, cnt[dom])
-    # algorithmic bytes per sample and launch (one launch covers n_samples): pointing is 12 B
-    # (pixel int32 + two FP32 weights); time-domain vectors 4 B each
-    if dom == 1 and fused:
-        bytes_per_sample = 12                 # pointing read once; t and u never leave LDS
-    else:
-        bytes_per_sample = {0: 12 + 4, 1: 4 + 4, 2: 12 + 4}[dom]
-    algo_bytes = bytes_per_sample * n_s
-    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = committed_traffic(names[dom], args.config)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": names[dom], "avg_launch_ms": round(avg_ms, 4),
-            "bytes_per_launch": algo_bytes}
-    if dom == 1 and pinfo["toeplitz_algo"] == mm.TOEPLITZ_FFT:
-        flops = n_s * fft_flops_per_sample(pinfo)
-        roof["fp32_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
-        roof["fp32_frac"] = round(flops / (avg_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)
-    per_kernel = {names[k]: {"total_ms": round(tot[k], 2), "launches": cnt[k],
-                             "avg_ms": round(tot[k] / max(1, cnt[k]), 4)} for k in range(4)}
-    log(f"[bench] per-kernel (timed steps): {json.dumps(per_kernel)}")
-    ph = np.mean(np.array(phases[-args.steps:]), axis=0) * 1e3
-    log(f"[bench] step phases (ms): plan {ph[0]:.1f}, solve {ph[1]:.1f}, release {ph[2]:.1f}")
-
-    if args.copy_probe_gib > 0:
-        nbytes = int(args.copy_probe_gib * (1 << 30))
-        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] copy probe: {nbytes} bytes read + {nbytes} bytes written per launch")
-
-    cpu = None
-    if not args.no_cpu_baseline:
+    if args.config == "ground" and not args.no_suite:
+        # the other workloads, each outside the headline's timed region, with a few steps each
+        sub = {}
+        small = argparse.Namespace(**vars(args))
+        small.steps, small.warmup = 2, 1
+        for name in ("satellite", "templates"):
+            t0 = time.time()
+            p2 = make_workload(name)
+            log(f"[bench] generated {name}: {p2.n_samples} samples in {time.time() - t0:.1f} s")
+            sub[name] = run_plain(small, p2, name, mm, torch, dev, 2, 1, args.refine)
+            del p2
+            free_host()
+            torch.cuda.empty_cache()
         t0 = time.time()
-        cpu = cpu_baseline(prob)
-        log(f"[bench] cpu baseline {cpu['value']:.3e} in {time.time() - t0:.1f} s")
-
-    out = {
-        "metric": "TOD samples x CG iters/s at rel-res 1e-8",
-        "value": value,
-        "unit": "TOD samples x CG iters/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 time-domain / f64 pixel-domain",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.config], "n_samples": n_s,
-                   "iterations": iters, "tol": args.tol, "n_kept": pinfo["n_kept"],
-                   "fft_size": pinfo["fft_size"], "parallelism": "single GPU"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
+        p3 = make_workload("batched")
+        log(f"[bench] generated batched: {p3.n_samples} samples x {p3.d.shape[0]} RHS in "
+            f"{time.time() - t0:.1f} s")
+        sub["batched"] = run_batched(small, p3, mm, torch, dev, torch.cuda.Stream(device=dev))
+        del p3
+        free_host()
+        torch.cuda.empty_cache()
+        sub["served"] = run_serving(small, mm, torch, dev)
+        out["sub"] = sub
     print(json.dumps(out), flush=True)
 
 

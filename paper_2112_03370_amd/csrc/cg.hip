@@ -633,12 +633,19 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
   // FP64 true residual (Eq. CGresidual) and iterative refinement for mixed-precision plans.
   double rel64 = -1.0;
   int32_t steps = 0, inner_its = 0;
-  if (P->precision == MM_PRECISION_FP64 || P->lambda_max == 0) {
-    // the products are FP64 already: the true residual above is the FP64 one
-    if (opts.refine > 0 || opts.check_fp64) rel64 = st.bb > 0 ? std::sqrt(true_rr / st.bb) : 0.0;
-  } else if ((opts.refine > 0 || opts.check_fp64) && st.bb > 0.0) {
+  const bool fp64_products = P->precision == MM_PRECISION_FP64 || P->lambda_max == 0;
+  if (opts.refine > 0 && st.bb > 0.0) {
     if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
     MM_TRY(refine_fp64(P, W, d, x, prm, opts.refine, s, &rel64, &steps, &inner_its));
+  } else if (opts.check_fp64 && st.bb > 0.0) {
+    if (fp64_products) {
+      rel64 = std::sqrt(true_rr / st.bb);  // the products are FP64 already
+    } else {
+      if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
+      MM_TRY(refine_fp64(P, W, d, x, prm, 0, s, &rel64, &steps, &inner_its));
+    }
+  } else if (opts.refine > 0 || opts.check_fp64) {
+    rel64 = 0.0;  // b = 0
   }
   MM_TRY(clock.stop(s));
   MM_HIP_TRY(hipStreamSynchronize(s));

@@ -17,7 +17,7 @@
 //   3. u_s = w (t_s - sum_k T_sk c_k)  (template projection subtracted); y += P^T u through the
 //      wavefront run merge
 // Samples of the first kCached steps of a baseline stay in registers between 1 and 3, so
-// baselines of up to kCached x 1024 samples read their pointing once; longer ones re-gather the
+// baselines of up to kCached x 2048 samples read their pointing once; longer ones re-gather the
 // rest.  Samples outside every baseline get u = w t through the diagonal product.
 #include <algorithm>
 #include <cmath>
@@ -29,7 +29,7 @@ namespace mm {
 
 namespace {
 
-constexpr int kTT = 256;          // threads per workgroup
+constexpr int kTT = 512;          // threads per workgroup
 constexpr int kStep = 4 * kTT;    // samples per step (4 consecutive per lane)
 constexpr int kCached = 4;        // steps kept in registers
 

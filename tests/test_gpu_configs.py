@@ -1,26 +1,24 @@
 """Map parity at the shapes of the ground-like and satellite-like workloads (GPU vs FP64 oracle).
 
 Each case keeps every per-detector dimension of its workload and slices the focal plane:
-  * ground-like: 16 of the 256 detectors, each 2^20 samples in 16 intervals of 2^16, 512 x 512
+  * ground-like: 32 of the 256 detectors, each 2^20 samples in 16 intervals of 2^16, 512 x 512
     patch, lambda 8192 (FFT length 2^15, the register-resident fused product);
-  * satellite-like: 2 of the 32 detectors, each 2^23 samples in 8 intervals of 2^20, 786,432
+  * satellite-like: 4 of the 32 detectors, each 2^23 samples in 8 intervals of 2^20, 786,432
     pixels, HWP, lambda 2^15 (FFT length 2^17, the four-step long-band product).
-The slice keeps the oracle's full PCG solve (its FP64 products take ~1 s per 16.8 M samples on
-the host cores) inside a couple of minutes per case.
 
 Checks, with tolerances derived from the arithmetic:
   * kept pixel ids and hit counts: bit-exact;
-  * the refined GPU map (FP64 true residual < 1e-8, the standard the oracle's map meets with its
-    recursive 1e-8) against the oracle's FP64 map at 1e-8: relative L2 <= 1e-6; two maps with
-    FP64 residuals <= 1e-8 differ by at most 2 kappa_eff 1e-8, and kappa_eff (map error over
-    residual) is ~16 on the 16-detector ground slice (143 iterations);
-  * the plain GPU map (recursive 1e-8, FP64 true residual ~6e-8: the FP32 product floor)
-    against the same oracle map: relative L2 <= 3e-6, the same bound with its ~6x larger
-    residual; iteration counts within 2;
+  * the reference is the oracle's PCG run on to relative residual 1e-10 (its iterate at the
+    first residual below 1e-8 gives Alg. 1's iteration count at 1e-8, compared within 2);
+  * the refined GPU map (FP64 true residual < 1e-8) against the reference: relative L2 <= 1e-6.
+    A map whose FP64 residual is r lies within kappa_eff r of the exact solution; the maps at a
+    recursive 1e-8 differ from each other by ~1e-6 on these slices (kappa_eff up to ~100, from
+    the 1/f noise weighting), so the reference is taken 100x tighter;
+  * the plain GPU map (recursive 1e-8; FP64 true residual ~2-6e-8, the FP32 product floor)
+    against the reference: relative L2 <= 3e-6 (kappa_eff times its residual);
   * the GPU map's FP64 true residual ||b - A x|| / ||b|| recomputed by the oracle: below 2e-7
-    (the FP32 product floor, ~5e-8 measured), and equal to the library's own FP64 exit check to
-    1e-4 relative;
-  * with one refinement step: the oracle's FP64 true residual of the refined map < 1e-8.
+    and equal to the library's own FP64 exit check to 1e-4 relative; after one refinement step
+    the oracle's FP64 true residual of the refined map is < 1e-8.
 """
 
 import numpy as np
@@ -38,7 +36,7 @@ def _dev(a):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("name,n_dets", [("ground", 16), ("satellite", 2)])
+@pytest.mark.parametrize("name,n_dets", [("ground", 32), ("satellite", 4)])
 def test_workload_slice_map_parity(gpu_lib, name, n_dets):
     prob = synth.make_config(name, n_dets=n_dets)
     print(f"[{name}] {prob.n_samples} samples, {n_dets} detectors", flush=True)
@@ -60,11 +58,12 @@ def test_workload_slice_map_parity(gpu_lib, name, n_dets):
     print(f"[{name}] oracle FP64 residuals: plain {r_gpu:.2e}, refined {r_ref:.2e}", flush=True)
     assert r_gpu < 2e-7 and abs(info["true_relres64"] - r_gpu) <= 1e-4 * r_gpu
     assert r_ref < 1e-8 and info_r["converged"] == 1
-    res = O.pcg(ref, b, tol=1e-8)
+    res = O.pcg(ref, b, tol=1e-10)
+    it8 = 1 + next(i for i, h in enumerate(res.history) if h < 1e-8)
     err = np.linalg.norm(m - res.x) / np.linalg.norm(res.x)
     err_r = np.linalg.norm(mr - res.x) / np.linalg.norm(res.x)
-    print(f"[{name}] oracle: {res.iterations} iterations; map rel L2 plain {err:.2e}, "
-          f"refined {err_r:.2e}", flush=True)
-    assert res.converged and abs(info["iterations"] - res.iterations) <= 2
+    print(f"[{name}] oracle: {it8} iterations to 1e-8, {res.iterations} to 1e-10; map rel L2 "
+          f"plain {err:.2e}, refined {err_r:.2e}", flush=True)
+    assert res.converged and abs(info["iterations"] - it8) <= 2
     assert err_r <= 1e-6
     assert err <= 3e-6
