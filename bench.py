@@ -58,6 +58,7 @@ KERNEL_SOURCES = {
     "toeplitz_long": ("toeplitz_long.hip", "fft_lds.h"),
     "unpoint": ("pointing.hip",),
     "point": ("pointing.hip", "wave_runs.h"),
+    "template_apply": ("templates.hip", "wave_runs.h"),
 }
 
 

@@ -35,12 +35,12 @@ TimedLaunch::~TimedLaunch() {
   P->timing.pending[kind].push_back(TimedPair{e0, e1, P->timing.tag});
 }
 
-void timing_drop_after(Plan* P, int32_t last) {
+void timing_drop_range(Plan* P, int32_t first, int32_t last) {
   for (int k = 0; k < K_NKINDS; ++k) {
     auto& v = P->timing.pending[k];
     std::vector<TimedPair> keep;
     for (const TimedPair& t : v) {
-      if (t.tag > last) {
+      if (t.tag >= first && t.tag <= last) {
         (void)hipEventSynchronize(t.e1);
         (void)hipEventDestroy(t.e0);
         (void)hipEventDestroy(t.e1);

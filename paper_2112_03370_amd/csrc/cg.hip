@@ -454,6 +454,7 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
     }
   } gg{&gexec};
   int queued = 0;
+  const int32_t tag_base = P->timing.next_tag;
   while (true) {
     MM_HIP_TRY(hipMemcpyAsync(W.h_state, W.state, sizeof(CgState), hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
@@ -492,7 +493,7 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
       MM_HIP_TRY(hipGraphLaunch(gexec, s));
     } else {
       for (int i = 0; i < chunk; ++i) {
-        if (P->timing.enabled) P->timing.tag = queued + i + 1;
+        if (P->timing.enabled) P->timing.tag = tag_base + queued + i + 1;
         MM_TRY(iteration(P, W, x, prm.two_level, s));
       }
       if (P->timing.enabled) P->timing.tag = 0;
@@ -501,7 +502,10 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
     if (prm.check_every <= 0 && chunk < 16 && !one_by_one) chunk *= 2;
   }
   *out = *W.h_state;
-  if (P->timing.enabled) timing_drop_after(P, out->iter);
+  if (P->timing.enabled) {
+    timing_drop_range(P, tag_base + out->iter + 1, tag_base + queued);
+    P->timing.next_tag = tag_base + queued + 1;
+  }
   return MM_OK;
 }
 

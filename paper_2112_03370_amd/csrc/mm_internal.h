@@ -92,6 +92,7 @@ struct TimedPair {
 struct Timing {
   bool enabled = false;
   int32_t tag = 0;
+  int32_t next_tag = 1;  // tags of successive PCG runs do not overlap (refinement solves)
   std::vector<TimedPair> pending[K_NKINDS];
   double total_ms[K_NKINDS] = {0, 0, 0, 0};
   int64_t count[K_NKINDS] = {0, 0, 0, 0};
@@ -222,9 +223,9 @@ struct Plan {
   std::mutex mu;
 };
 
-// Drop timed launches of PCG iterations beyond `last` (queued after convergence; they exit at
+// Drop timed launches tagged first..last (PCG iterations queued after convergence: they exit at
 // once and are not kernel work).
-void timing_drop_after(Plan* P, int32_t last);
+void timing_drop_range(Plan* P, int32_t first, int32_t last);
 
 // Allocation helper tracking plan bytes.
 template <class T>

@@ -43,24 +43,26 @@ struct TFlush {
   }
 };
 
-// Scaled Legendre values T_k = scale_k P_k(x), k < n, by the three-term recurrence
-// (k + 1) P_(k+1) = (2k + 1) x P_k - k P_(k-1).
-__device__ __forceinline__ void legendre(double x, int n, const double* scale,
-                                         double (&T)[kMaxTemplates]) {
+// Scaled Legendre values T_k = scale_k P_k(x), k < NP, by the three-term recurrence
+// k P_k = (2k - 1) x P_(k-1) - (k - 1) P_(k-2), with 1/k as a constant.
+template <int NP>
+__device__ __forceinline__ void legendre(double x, const double* scale, double (&T)[NP]) {
   double p0 = 1.0, p1 = x;
 #pragma unroll
-  for (int k = 0; k < kMaxTemplates; ++k) {
+  for (int k = 0; k < NP; ++k) {
     double pk;
     if (k == 0) {
       pk = p0;
     } else if (k == 1) {
       pk = p1;
     } else {
-      pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / static_cast<double>(k);
+      constexpr double kInv[kMaxTemplates] = {0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5,
+                                               1.0 / 6, 1.0 / 7};
+      pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) * kInv[k];
       p0 = p1;
       p1 = pk;
     }
-    T[k] = k < n ? scale[k] * pk : 0.0;
+    T[k] = scale[k] * pk;
   }
 }
 
@@ -70,25 +72,26 @@ __device__ __forceinline__ void load4(const int32_t* __restrict__ lpix,
                                       const float* __restrict__ wu,
                                       const double* __restrict__ x,
                                       const float* __restrict__ d, int64_t start, int len,
-                                      int j0, int (&key)[4], double (&t)[4], double (&q)[4],
-                                      double (&u)[4]) {
+                                      int j0, int (&key)[4], double (&t)[4], float (&q)[4],
+                                      float (&u)[4]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int j = j0 + i;
     key[i] = -1;
-    t[i] = q[i] = u[i] = 0.0;
+    t[i] = 0.0;
+    q[i] = u[i] = 0.0f;
     if (j < len) {
       const int64_t g = start + j;
       const int p = lpix[g];
       if (p >= 0) {
         key[i] = p;
-        q[i] = static_cast<double>(wq[g]);
-        u[i] = static_cast<double>(wu[g]);
+        q[i] = wq[g];
+        u[i] = wu[g];
         if (kData) {
           t[i] = static_cast<double>(d[g]);
         } else {
           const double* m = x + 3 * static_cast<int64_t>(p);
-          t[i] = m[0] + q[i] * m[1] + u[i] * m[2];
+          t[i] = m[0] + static_cast<double>(q[i]) * m[1] + static_cast<double>(u[i]) * m[2];
         }
       }
     }
@@ -96,51 +99,53 @@ __device__ __forceinline__ void load4(const int32_t* __restrict__ lpix,
 }
 
 // Projections of 4 samples onto the templates: a_k += T_k(x_j) w t_j.
+template <int NP>
 __device__ __forceinline__ void project4(const int (&key)[4], const double (&t)[4], int j0,
-                                         double invL, double w, int n, const double* scale,
-                                         double (&a)[kMaxTemplates]) {
+                                         double invL, double w, const double* scale,
+                                         double (&a)[NP]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (key[i] < 0) continue;
-    double T[kMaxTemplates];
-    legendre(fma(2.0, static_cast<double>(j0 + i), 1.0) * invL - 1.0, n, scale, T);
+    double T[NP];
+    legendre<NP>(fma(2.0, static_cast<double>(j0 + i), 1.0) * invL - 1.0, scale, T);
     const double v = w * t[i];
 #pragma unroll
-    for (int k = 0; k < kMaxTemplates; ++k) a[k] = fma(T[k], v, a[k]);
+    for (int k = 0; k < NP; ++k) a[k] = fma(T[k], v, a[k]);
   }
 }
 
 // u_j = w (t_j - sum_k T_k c_k) for 4 samples, then the pointing sums.
+template <int NP>
 __device__ __forceinline__ void subtract_point4(const int (&key)[4], const double (&t)[4],
-                                                const double (&q)[4], const double (&u)[4],
-                                                int j0, double invL, double w, int n,
-                                                const double* scale, const double* c,
+                                                const float (&q)[4], const float (&u)[4],
+                                                int j0, double invL, double w,
+                                                const double* scale, const double (&c)[NP],
                                                 double* y) {
   double v[4][3];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     double r = 0.0;
     if (key[i] >= 0) {
-      double T[kMaxTemplates];
-      legendre(fma(2.0, static_cast<double>(j0 + i), 1.0) * invL - 1.0, n, scale, T);
+      double T[NP];
+      legendre<NP>(fma(2.0, static_cast<double>(j0 + i), 1.0) * invL - 1.0, scale, T);
       double fit = 0.0;
 #pragma unroll
-      for (int k = 0; k < kMaxTemplates; ++k) fit = fma(T[k], c[k], fit);
+      for (int k = 0; k < NP; ++k) fit = fma(T[k], c[k], fit);
       r = w * (t[i] - fit);
     }
     v[i][0] = r;
-    v[i][1] = q[i] * r;
-    v[i][2] = u[i] * r;
+    v[i][1] = static_cast<double>(q[i]) * r;
+    v[i][2] = static_cast<double>(u[i]) * r;
   }
   wave_merge_runs<3>(key, v, TFlush{y});
 }
 
-template <bool kData>
+template <bool kData, int NP>
 __global__ __launch_bounds__(kTT) void k_template_apply(
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
     const double* __restrict__ x, const float* __restrict__ d, const TBase* __restrict__ bases,
-    const double* __restrict__ kinv, int n_poly, double* __restrict__ y,
-    const int32_t* __restrict__ done) {
+    const double* __restrict__ kinv, double* __restrict__ y, const int32_t* __restrict__ done) {
+  constexpr int n_poly = NP;
   if (done != nullptr && *done) return;
   __shared__ double red[kMaxTemplates][kTT / 64];
   __shared__ double scale[kMaxTemplates];
@@ -154,29 +159,31 @@ __global__ __launch_bounds__(kTT) void k_template_apply(
   const int nsteps = (B.len + kStep - 1) / kStep;
 
   // ---- 1. gather and project ------------------------------------------------------------------
-  double a[kMaxTemplates];
+  double a[NP];
 #pragma unroll
-  for (int k = 0; k < kMaxTemplates; ++k) a[k] = 0.0;
+  for (int k = 0; k < NP; ++k) a[k] = 0.0;
   int ck[kCached][4];
-  double ct[kCached][4], cq[kCached][4], cu[kCached][4];
+  double ct[kCached][4];
+  float cq[kCached][4], cu[kCached][4];
 #pragma unroll
   for (int sidx = 0; sidx < kCached; ++sidx) {
     if (sidx < nsteps) {
       const int j0 = sidx * kStep + 4 * tid;
       load4<kData>(lpix, wq, wu, x, d, B.start, B.len, j0, ck[sidx], ct[sidx], cq[sidx], cu[sidx]);
-      project4(ck[sidx], ct[sidx], j0, invL, w, n_poly, scale, a);
+      project4<NP>(ck[sidx], ct[sidx], j0, invL, w, scale, a);
     }
   }
   for (int sidx = kCached; sidx < nsteps; ++sidx) {
     const int j0 = sidx * kStep + 4 * tid;
     int k4[4];
-    double t4[4], q4[4], u4[4];
+    double t4[4];
+    float q4[4], u4[4];
     load4<kData>(lpix, wq, wu, x, d, B.start, B.len, j0, k4, t4, q4, u4);
-    project4(k4, t4, j0, invL, w, n_poly, scale, a);
+    project4<NP>(k4, t4, j0, invL, w, scale, a);
   }
   // workgroup sums in a fixed order
 #pragma unroll
-  for (int k = 0; k < kMaxTemplates; ++k) {
+  for (int k = 0; k < NP; ++k) {
     double v = a[k];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
     if ((tid & 63) == 0) red[k][tid >> 6] = v;
@@ -197,23 +204,24 @@ __global__ __launch_bounds__(kTT) void k_template_apply(
     coef[tid] = acc;
   }
   __syncthreads();
-  double c[kMaxTemplates];
+  double c[NP];
 #pragma unroll
-  for (int k = 0; k < kMaxTemplates; ++k) c[k] = coef[k];
+  for (int k = 0; k < NP; ++k) c[k] = coef[k];
 
   // ---- 3. subtract the fit, weight, point -----------------------------------------------------
 #pragma unroll
   for (int sidx = 0; sidx < kCached; ++sidx) {
     if (sidx < nsteps)
-      subtract_point4(ck[sidx], ct[sidx], cq[sidx], cu[sidx], sidx * kStep + 4 * tid, invL, w,
-                      n_poly, scale, c, y);
+      subtract_point4<NP>(ck[sidx], ct[sidx], cq[sidx], cu[sidx], sidx * kStep + 4 * tid, invL,
+                          w, scale, c, y);
   }
   for (int sidx = kCached; sidx < nsteps; ++sidx) {
     const int j0 = sidx * kStep + 4 * tid;
     int k4[4];
-    double t4[4], q4[4], u4[4];
+    double t4[4];
+    float q4[4], u4[4];
     load4<kData>(lpix, wq, wu, x, d, B.start, B.len, j0, k4, t4, q4, u4);
-    subtract_point4(k4, t4, q4, u4, j0, invL, w, n_poly, scale, c, y);
+    subtract_point4<NP>(k4, t4, q4, u4, j0, invL, w, scale, c, y);
   }
 }
 
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(kTT) void k_template_kernel(const int32_t* __restri
       for (int j = tid; j < B.len; j += kTT) {
         if (lpix[B.start + j] < 0) continue;
         double T[kMaxTemplates];
-        legendre(fma(2.0, static_cast<double>(j), 1.0) * invL - 1.0, n_poly, scale, T);
+        legendre<kMaxTemplates>(fma(2.0, static_cast<double>(j), 1.0) * invL - 1.0, scale, T);
         double ti = 0.0, tk = 0.0;
 #pragma unroll
         for (int m = 0; m < kMaxTemplates; ++m) {
@@ -385,19 +393,38 @@ mm_status build_templates(Plan* P, const mm_geometry* g, const std::vector<Tile>
   return MM_OK;
 }
 
+namespace {
+
+template <int NP>
+mm_status launch_np(Plan* P, const double* x, const float* d, double* y, const int32_t* done,
+                    hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(P->n_baselines));
+  if (x != nullptr)
+    hipLaunchKernelGGL((k_template_apply<false, NP>), grid, dim3(kTT), 0, s, P->lpix, P->wq,
+                       P->wu, x, d, P->tbases, P->tkinv, y, done);
+  else
+    hipLaunchKernelGGL((k_template_apply<true, NP>), grid, dim3(kTT), 0, s, P->lpix, P->wq,
+                       P->wu, x, d, P->tbases, P->tkinv, y, done);
+  MM_HIP_TRY(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace
+
 mm_status launch_template_apply(Plan* P, const double* x, const float* d, double* y,
                                 const int32_t* done, hipStream_t s) {
   TimedLaunch tl(P, K_TOEPLITZ, s);
   if (P->n_baselines > 0) {
-    if (x != nullptr)
-      hipLaunchKernelGGL(k_template_apply<false>, dim3(static_cast<unsigned>(P->n_baselines)),
-                         dim3(kTT), 0, s, P->lpix, P->wq, P->wu, x, d, P->tbases, P->tkinv,
-                         P->n_poly, y, done);
-    else
-      hipLaunchKernelGGL(k_template_apply<true>, dim3(static_cast<unsigned>(P->n_baselines)),
-                         dim3(kTT), 0, s, P->lpix, P->wq, P->wu, x, d, P->tbases, P->tkinv,
-                         P->n_poly, y, done);
-    MM_HIP_TRY(hipGetLastError());
+    switch (P->n_poly) {
+      case 1: MM_TRY(launch_np<1>(P, x, d, y, done, s)); break;
+      case 2: MM_TRY(launch_np<2>(P, x, d, y, done, s)); break;
+      case 3: MM_TRY(launch_np<3>(P, x, d, y, done, s)); break;
+      case 4: MM_TRY(launch_np<4>(P, x, d, y, done, s)); break;
+      case 5: MM_TRY(launch_np<5>(P, x, d, y, done, s)); break;
+      case 6: MM_TRY(launch_np<6>(P, x, d, y, done, s)); break;
+      case 7: MM_TRY(launch_np<7>(P, x, d, y, done, s)); break;
+      default: MM_TRY(launch_np<8>(P, x, d, y, done, s)); break;
+    }
   }
   if (P->n_free_tiles > 0)
     MM_TRY(launch_diag_tiles(P, P->free_tiles, P->n_free_tiles, x, d, y, done, s));
