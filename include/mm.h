@@ -207,29 +207,47 @@ mm_status mm_plan_info(const mm_plan_t* plan, mm_plan_info_t* out);
  * ids and their hit counts (unflagged samples).  Bit-exact integers.  Synchronous. */
 mm_status mm_plan_pixels(const mm_plan_t* plan, int64_t* global_ids, int32_t* hits);
 
-/* t = P x (un-pointing, MAPMAT).  x DEVICE double [n_kept][3]; t DEVICE float [n_samples];
- * gap samples get 0.  Sums in FP64, stored FP32.  Asynchronous. */
+/* t = P x: the un-pointing step of the system product (the pointing matrix of
+ * Eq. dataModelSingleSlot / Eq. dataModelHwp applied to a map; first of the three operations of
+ * the right-to-left product in the solvers section).  x DEVICE double [n_kept][3]; t DEVICE
+ * float [n_samples]; gap samples get 0.  Sums in FP64, stored FP32.  Asynchronous.  Errors:
+ * MM_ERR_INVALID (NULL plan or vector, wrong device), MM_ERR_HIP. */
 mm_status mm_unpoint(const mm_plan_t* plan, const double* x, float* t, void* stream);
 
-/* u = N^-1 t (block-diagonal banded Toeplitz; identity outside blocks; truncated at block
- * edges).  t, u DEVICE float [n_samples], must not alias.  FP32.  Asynchronous. */
+/* u = N^-1 t: the block-diagonal banded Toeplitz product of the inverse noise weights
+ * (Eq. MADCAP; the stbmm product of the Toeplitz algebra package: identity outside blocks,
+ * truncated at block edges, shift-and-overlap segments of the plan's FFT length).  Template
+ * plans apply F_T of Eq. defFT on the same call path only inside mm_apply_A / mm_rhs; here they
+ * apply the diagonal weights.  t, u DEVICE float [n_samples], must not alias.  FP32.
+ * Asynchronous.  Errors: MM_ERR_INVALID (NULL, aliasing, wrong device), MM_ERR_HIP. */
 mm_status mm_noise_weight(const mm_plan_t* plan, const float* t, float* u, void* stream);
 
-/* y = P^T u (pointing, MAPMAT): y[p] = sum over samples of p of (1, cos, sin) u_s, FP64
- * accumulation.  y DEVICE double [n_kept][3] is overwritten.  Asynchronous. */
+/* y = P^T u: the pointing (binning) step, last of the three operations of the system product:
+ * y[p] = sum over samples of p of (1, cos 2psi, sin 2psi) u_s, FP64 accumulation.  u DEVICE
+ * float [n_samples]; y DEVICE double [n_kept][3] is overwritten.  Asynchronous.  Errors:
+ * MM_ERR_INVALID, MM_ERR_HIP. */
 mm_status mm_point(const mm_plan_t* plan, const float* u, double* y, void* stream);
 
-/* b = P^T N^-1 d for k right-hand sides; d DEVICE float, column j at d + j*ld_d (ld_d >=
- * n_samples); gap samples of d are ignored.  b DEVICE double [k][n_kept][3].  Asynchronous. */
+/* b = P^T F_T d, the right-hand side of Eq. genMapEstimator (F_T = N^-1 for the
+ * maximum-likelihood system, Eq. defFT for template plans), for k right-hand sides; d DEVICE
+ * float, column j at d + j*ld_d (ld_d >= n_samples); gap samples of d are ignored.  b DEVICE
+ * double [k][n_kept][3].  FP64 products on MM_PRECISION_FP64 and template plans (synchronous
+ * there), else FP32 time domain.  Asynchronous otherwise.  Errors: MM_ERR_INVALID, MM_ERR_OOM,
+ * MM_ERR_HIP. */
 mm_status mm_rhs(const mm_plan_t* plan, const float* d, int32_t k, int64_t ld_d, double* b,
                  void* stream);
 
-/* y = P^T N^-1 P x (the system product, applied right to left), k columns.  x, y DEVICE
- * double [k][n_kept][3], must not alias.  Asynchronous. */
+/* y = P^T F_T P x, the system matrix of Eq. genMapEstimator applied right to left as the
+ * solvers section describes (un-pointing, noise weighting / template filter, pointing), k
+ * columns.  x, y DEVICE double [k][n_kept][3], must not alias.  Precision as mm_rhs.
+ * Asynchronous (synchronous for FP64 products).  Errors: MM_ERR_INVALID, MM_ERR_OOM,
+ * MM_ERR_HIP. */
 mm_status mm_apply_A(const mm_plan_t* plan, const double* x, double* y, int32_t k,
                      void* stream);
 
-/* z = M_BD r, per pixel 3x3 FP64.  r, z DEVICE double [k][n_kept][3] (may alias).  Async. */
+/* z = M_BD r, the block-Jacobi preconditioner (P^T diag(N^-1) P)^-1 of the preconditioner
+ * section: one symmetric 3x3 FP64 block per kept pixel, inverted at plan time.  r, z DEVICE
+ * double [k][n_kept][3] (may alias).  Asynchronous.  Errors: MM_ERR_INVALID, MM_ERR_HIP. */
 mm_status mm_precond_bj(const mm_plan_t* plan, const double* r, double* z, int32_t k,
                         void* stream);
 
