@@ -54,6 +54,7 @@ def log(*a):
 KERNEL_SOURCES = {
     "apply_fused": ("apply_fused.hip", "fft_lds.h", "segment_io.h", "wave_runs.h"),
     "apply_reg": ("apply_reg.hip", "fft_lds.h", "segment_io.h", "wave_runs.h"),
+    "apply_long": ("toeplitz_long.hip", "fft_lds.h", "segment_io.h", "wave_runs.h"),
     "toeplitz": ("toeplitz.hip", "fft_lds.h"),
     "toeplitz_long": ("toeplitz_long.hip", "fft_lds.h"),
     "unpoint": ("pointing.hip",),
@@ -64,8 +65,9 @@ KERNEL_SOURCES = {
 
 def fused_kernel(pinfo):
     """Name of the fused product kernel a plan runs: register-resident FFT (2^15-sample
-    segments with at most 2^14 outputs) or LDS-resident FFT."""
-    return "apply_reg" if pinfo["fused"] == 2 else "apply_fused"
+    segments with at most 2^14 outputs), persistent four-step FFT (2^16 and 2^17-sample
+    segments) or LDS-resident FFT."""
+    return {2: "apply_reg", 3: "apply_long"}.get(pinfo["fused"], "apply_fused")
 
 
 def plan_flags(args):

@@ -78,7 +78,8 @@ typedef struct mm_server mm_server_t;
  *   toeplitz_algo  MM_TOEPLITZ_*; fft_size  real FFT length for the overlap-save product
  *               (power of two in [2^11, 2^17], > 2 lambda_max), 0 = automatic.  Lengths up
  *               to 2^15 run in one CU's LDS (fused with the pointing products); 2^16 and 2^17
- *               (lambda up to 2^15) use a four-step transform through a device tile.
+ *               (lambda up to 2^15 and beyond) use a four-step transform through one device
+ *               tile per CU, fused with the pointing products as well.
  *   flags       MM_FLAG_* bits.
  *   precision   MM_PRECISION_*.
  *   n_poly, n_baselines, base_start, base_len
@@ -142,7 +143,8 @@ typedef struct {
   int32_t n_blocks;
   int32_t n_chunks;       /* overlap-save segments (FFT) or tiles (direct) per product */
   int32_t fused;          /* 1: gather, Toeplitz and scatter run as one kernel per segment
-                             (LDS-resident FFT), 2: the same with the register-resident FFT */
+                             (LDS-resident FFT), 2: the same with the register-resident FFT,
+                             3: the same with the four-step FFT of long segments */
   int32_t precision;      /* MM_PRECISION_* of the plan */
   int32_t n_poly;         /* template orders per baseline (0: maximum-likelihood system) */
   int64_t n_baselines;

@@ -147,7 +147,9 @@ mm_status mm_plan_info(const mm_plan_t* plan, mm_plan_info_t* out) {
   out->fft_size = P->algo == MM_TOEPLITZ_FFT ? P->fft_n : 0;
   out->n_blocks = P->n_blocks;
   out->n_chunks = P->n_chunks;
-  out->fused = (P->lambda_max > 0 && P->algo == MM_TOEPLITZ_FFT && P->fused) ? (P->reg_fft ? 2 : 1) : 0;
+  out->fused = (P->lambda_max > 0 && P->algo == MM_TOEPLITZ_FFT && P->fused)
+                   ? (long_fft_size(P->fft_n) ? 3 : (P->reg_fft ? 2 : 1))
+                   : 0;
   out->precision = P->precision;
   out->n_poly = P->n_poly;
   out->n_baselines = P->n_baselines;

@@ -160,12 +160,15 @@ mm_status launch(Plan* P, const double* x, const float* d, int64_t ldx, double* 
 }  // namespace
 
 mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
-                             const int32_t* done, hipStream_t s, int32_t ncol, int64_t ldx,
-                             int64_t ldy) {
+                             const int32_t* done, hipStream_t s, float2* tiles, int32_t ncol,
+                             int64_t ldx, int64_t ldy) {
   if (P->n_kept == 0 || ncol <= 0) return MM_OK;
   if (ldx == 0) ldx = d != nullptr ? P->n_samples : 3 * P->n_kept;
   if (ldy == 0) ldy = 3 * P->n_kept;
-  if (P->n_chunks > 0 && P->reg_fft) {
+  if (P->n_chunks > 0 && long_fft_size(P->fft_n)) {
+    TimedLaunch tl(P, K_TOEPLITZ, s);
+    MM_TRY(launch_apply_long(P, x, d, ldx, y, ldy, ncol, tiles, done, s));
+  } else if (P->n_chunks > 0 && P->reg_fft) {
     TimedLaunch tl(P, K_TOEPLITZ, s);
     MM_TRY(launch_apply_reg(P, x, d, ldx, y, ldy, ncol, done, s));
   } else if (P->n_chunks > 0) {

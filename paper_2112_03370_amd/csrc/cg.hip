@@ -280,7 +280,7 @@ mm_status iteration(Plan* P, Work& W, double* x, bool two_level, hipStream_t s) 
     // synchronous and not gated by `done`: such plans run one iteration per host check
     MM_TRY(exact_product(P, W.p, nullptr, W.q, s));
   } else if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
-    MM_TRY(launch_apply_fused(P, W.p, nullptr, W.q, done, s));
+    MM_TRY(launch_apply_fused(P, W.p, nullptr, W.q, done, s, W.scratch));
   } else {
     MM_TRY(launch_unpoint(P, W.p, W.t, done, s));
     MM_TRY(launch_noise_weight(P, W.t, W.u, W.scratch, done, s));
@@ -338,7 +338,7 @@ mm_status compute_rhs(Plan* P, Work& W, const float* d, double* b, hipStream_t s
   if (P->precision == MM_PRECISION_FP64) return exact_product(P, nullptr, d, b, s);
   if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
     MM_TRY(launch_zero(b, 3 * P->n_kept, s));
-    return launch_apply_fused(P, nullptr, d, b, nullptr, s);
+    return launch_apply_fused(P, nullptr, d, b, nullptr, s, W.scratch);
   }
   MM_TRY(launch_mask_data(P, d, W.t, s));
   MM_TRY(launch_noise_weight(P, W.t, W.u, W.scratch, nullptr, s));
@@ -358,7 +358,7 @@ mm_status apply_A(Plan* P, Work& W, const double* x, double* y, const int32_t* d
   if (P->precision == MM_PRECISION_FP64) return exact_product(P, x, nullptr, y, s);
   if (P->algo == MM_TOEPLITZ_FFT && P->fused) {
     MM_TRY(launch_zero(y, 3 * P->n_kept, s));
-    return launch_apply_fused(P, x, nullptr, y, done, s);
+    return launch_apply_fused(P, x, nullptr, y, done, s, W.scratch);
   }
   MM_TRY(launch_unpoint(P, x, W.t, done, s));
   MM_TRY(launch_noise_weight(P, W.t, W.u, W.scratch, done, s));
@@ -372,7 +372,7 @@ mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* 
   if (P->lambda_max != 0 && P->algo == MM_TOEPLITZ_FFT && P->fused &&
       P->precision == MM_PRECISION_MIXED) {
     for (int32_t j = 0; j < ncol; ++j) MM_TRY(launch_zero(y + j * ldy, 3 * P->n_kept, s));
-    return launch_apply_fused(P, x, nullptr, y, nullptr, s, ncol, ldx, ldy);
+    return launch_apply_fused(P, x, nullptr, y, nullptr, s, W.scratch, ncol, ldx, ldy);
   }
   for (int32_t j = 0; j < ncol; ++j) MM_TRY(apply_A(P, W, x + j * ldx, y + j * ldy, nullptr, s));
   return MM_OK;

@@ -105,7 +105,7 @@ struct Timing {
 struct Work {
   float* t = nullptr;           // [n_samples] (only when the product is not fused)
   float* u = nullptr;
-  float2* scratch = nullptr;    // long segments: one NC-point complex tile per segment
+  float2* scratch = nullptr;    // long segments: one NC-point complex tile per workgroup
   double* r = nullptr;          // [3 n_kept] each
   double* z = nullptr;
   double* p = nullptr;
@@ -185,7 +185,7 @@ struct Plan {
   int32_t* band_ncoef = nullptr;
   float* spec = nullptr;        // [n_bands][fft_n/2 + 1], scaled for the in-kernel transform
   float2* spec_reg = nullptr;   // symbol pairs in the register FFT kernel's read order
-  float2* long_pq = nullptr;    // spectrum-step coefficients in the long kernel's read order
+  float4* long_pq = nullptr;    // spectrum-step coefficient pairs in the long kernel's read order
   float2* tw0 = nullptr;        // fine twiddles exp(-2 pi i m / fft_n), m < 128
   float2* tw1 = nullptr;        // coarse twiddles exp(-2 pi i 128 m / fft_n)
   Chunk* chunks = nullptr;      // FFT segments or direct tiles
@@ -195,6 +195,7 @@ struct Plan {
   int32_t n_id_tiles = 0;
   bool fused = true;            // FFT path: gather + Toeplitz + scatter in one kernel
   bool reg_fft = false;         // fused 2^15 segments in the register-resident kernel
+  int32_t n_cu = 0;             // compute units of the plan's device
   std::atomic<int32_t> tuned_block{0};  // block size chosen by a tuned stacked solve (0: none)
   int32_t n_chunks = 0;
   int64_t* id_seg = nullptr;    // identity segments: pairs (start, len)
@@ -272,9 +273,10 @@ mm_status launch_diag_tiles(Plan* P, const Tile* tiles, int32_t n_tiles, const d
                             const float* d, double* y, const int32_t* done, hipStream_t s);
 // FFT path, fused: y += P^T N^-1 (P x) (d == nullptr) or y += P^T N^-1 d (x == nullptr), for
 // ncol columns (x or d column j at + j ldx, y column j at + j ldy; 0 = packed defaults).
+// Long segments (2^16, 2^17) need the solve's tiles.
 mm_status launch_apply_fused(Plan* P, const double* x, const float* d, double* y,
-                             const int32_t* done, hipStream_t s, int32_t ncol = 1,
-                             int64_t ldx = 0, int64_t ldy = 0);
+                             const int32_t* done, hipStream_t s, float2* tiles,
+                             int32_t ncol = 1, int64_t ldx = 0, int64_t ldy = 0);
 // Register-resident variant for 2^15-sample segments with at most 2^14 outputs (apply_reg.hip).
 bool apply_reg_supported(const Plan* P);
 mm_status build_reg_table(Plan* P, hipStream_t s);  // after the band spectra
@@ -364,5 +366,12 @@ int32_t long_fine_size();
 mm_status launch_toeplitz_long(Plan* P, const float* t, float* u, float2* scratch,
                                const int32_t* done, hipStream_t s);
 mm_status build_long_table(Plan* P, hipStream_t s);  // after the band spectra
+// Workgroups (and tiles) of the persistent long-segment kernels.
+int32_t long_slots(const Plan* P);
+// Fused long-segment product: y += P^T N^-1 (P x) or P^T N^-1 d for ncol columns (layout as
+// launch_apply_fused), through `tiles` (long_slots(P) tiles of fft_n / 2 points).
+mm_status launch_apply_long(Plan* P, const double* x, const float* d, int64_t ldx, double* y,
+                            int64_t ldy, int32_t ncol, float2* tiles, const int32_t* done,
+                            hipStream_t s);
 
 }  // namespace mm

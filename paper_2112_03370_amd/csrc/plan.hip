@@ -593,8 +593,8 @@ int32_t reduction_blocks(int64_t n_kept) {
 int64_t work_bytes(const Plan* P) {
   int64_t b = 0;
   if (needs_time_buffers(P)) b += 2 * P->n_samples * static_cast<int64_t>(sizeof(float));
-  if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n))
-    b += static_cast<int64_t>(P->n_chunks) * (P->fft_n / 2) * static_cast<int64_t>(sizeof(float2));
+  if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n) && P->n_chunks > 0)
+    b += static_cast<int64_t>(long_slots(P)) * (P->fft_n / 2) * static_cast<int64_t>(sizeof(float2));
   b += 5 * 3 * P->n_kept * static_cast<int64_t>(sizeof(double));
   b += 4 * static_cast<int64_t>(reduction_blocks(P->n_kept)) * sizeof(double);
   b += sizeof(CgState);
@@ -626,8 +626,8 @@ mm_status work_alloc(const Plan* P, Work* W) {
     MM_TRY(get(&W->t, static_cast<size_t>(P->n_samples)));
     MM_TRY(get(&W->u, static_cast<size_t>(P->n_samples)));
   }
-  if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n))
-    MM_TRY(get(&W->scratch, static_cast<size_t>(P->n_chunks) * (P->fft_n / 2)));
+  if (P->algo == MM_TOEPLITZ_FFT && long_fft_size(P->fft_n) && P->n_chunks > 0)
+    MM_TRY(get(&W->scratch, static_cast<size_t>(long_slots(P)) * (P->fft_n / 2)));
   const size_t nu = static_cast<size_t>(3 * P->n_kept);
   MM_TRY(get(&W->r, nu));
   MM_TRY(get(&W->z, nu));
@@ -714,6 +714,7 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
     }
   } guard{P};
   MM_HIP_TRY(hipGetDevice(&P->device));
+  MM_HIP_TRY(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
   P->n_samples = g->n_samples;
   P->n_pix_global = g->n_pix_global;
   P->lambda_max = lambda_max;
@@ -935,8 +936,6 @@ mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
   }
 
   // ---- workspace -----------------------------------------------------------------------------
-  if (algo == MM_TOEPLITZ_FFT && long_fft_size(fft_n))
-    P->fused = false;  // long segments: gather, four-step product and scatter as three kernels
   P->reg_fft = algo == MM_TOEPLITZ_FFT && P->fused && (g->flags & MM_FLAG_LDS_FFT) == 0 &&
                apply_reg_supported(P);
   if (P->reg_fft) MM_TRY(build_reg_table(P, s));

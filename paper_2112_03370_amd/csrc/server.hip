@@ -320,11 +320,14 @@ int64_t plan_estimate(const mm_geometry* g) {
     b += 4 * 65538;  // band spectrum upper bound (2^17 / 2 + 1)
     if (g->band_ncoef) lambda_max = std::max(lambda_max, g->band_ncoef[i] - 1);
   }
-  // unfused products (flag, direct product, or segments beyond 2^15): FP32 time-domain work
-  // vectors of the plan's workspace
-  const bool unfused = (g->flags & MM_FLAG_UNFUSED) != 0 || g->toeplitz_algo == MM_TOEPLITZ_DIRECT ||
-                       lambda_max > 12288;
+  // unfused products (flag or direct product): FP32 time-domain work vectors of the plan's
+  // workspace
+  const bool unfused = (g->flags & MM_FLAG_UNFUSED) != 0 || g->toeplitz_algo == MM_TOEPLITZ_DIRECT;
   if (unfused && lambda_max > 0) b += 8 * g->n_samples;
+  // segments beyond 2^15: the spectrum-step table (NC <= 2^16 points per band) and the tiles
+  // of the four-step transform (one per CU, at most 256 CUs)
+  if (!unfused && lambda_max > 12288)
+    b += (static_cast<int64_t>(g->n_bands) + 256) * 65536 * static_cast<int64_t>(sizeof(float2));
   return b;
 }
 

@@ -40,6 +40,12 @@ CASES = {
     "ground_lam8192_rhs3": lambda: synth.make_ground(cfg_id=65, n_dets=3, samples_per_det=70001,
                                                      interval=35001, side=24, lam=8192,
                                                      flag_frac=0.01, n_rhs=3),
+    # lambda = 2^14: 2^16-sample segments through the persistent four-step kernel, several
+    # columns sharing its workgroups
+    "satellite_lam16384_rhs2": lambda: synth.make_satellite(cfg_id=66, n_dets=2,
+                                                            samples_per_det=1 << 18,
+                                                            interval=1 << 17, n_rings=32,
+                                                            n_phi=64, lam=1 << 14, n_rhs=2),
 }
 
 _cache = {}
@@ -59,6 +65,8 @@ def test_apply_A_multi_column_parity(gpu_lib, name, unfused):
     plan = gpu_lib.Plan.from_problem(prob, flags=gpu_lib.FLAG_UNFUSED if unfused else 0)
     if name == "ground_lam8192_rhs3":
         assert plan.info["fused"] == (0 if unfused else 2), plan.info
+    if name.startswith("satellite"):
+        assert plan.info["fused"] == (0 if unfused else 3), plan.info
     X = np.random.default_rng(7).standard_normal((5, ref.n_kept, 3))
     Y = plan.apply_A(_dev(X)).cpu().numpy()
     for j in range(5):

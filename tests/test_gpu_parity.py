@@ -402,12 +402,37 @@ def test_noise_weight_long_band(gpu_lib, lam, fft_size):
     assert err <= 3e-6, err
 
 
+@pytest.mark.parametrize("fft_size,lam", [(65536, 12001), (131072, 20001), (131072, 32768)])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_apply_A_long_segments(gpu_lib, fft_size, lam, flags):
+    # fused (gather and scatter inside the four-step kernel) and unfused long-segment products:
+    # odd lambda and odd interval lengths (unaligned windows, ragged last segments), flagged
+    # samples, a gap between intervals; per-unknown bounds on A x and b
+    prob = synth.make_ground(cfg_id=27, n_dets=2, samples_per_det=300001, interval=200003,
+                             side=24, lam=lam, flag_frac=0.01)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=fft_size,
+                 flags=flags)
+    assert plan.info["fft_size"] == fft_size
+    assert plan.info["fused"] == (0 if flags else 3), plan.info
+    x = np.random.default_rng(11).standard_normal((ref.n_kept, 3))
+    y, want = plan.apply_A(_dev(x)).cpu().numpy(), O.apply_A(ref, x)
+    err = float(_rel(y, want))
+    assert err <= 3e-6, err
+    assert np.all(np.abs(y - want) <= _A_bound(plan, ref, O.unpoint(ref, x)))
+    b, bw = plan.rhs(_dev(prob.d[0])).cpu().numpy(), O.rhs(ref, prob.d[0])
+    err = float(_rel(b, bw))
+    assert err <= 3e-6, err
+    dm = np.where(ref.lpix >= 0, prob.d[0].astype(np.float64), 0.0)
+    assert np.all(np.abs(b - bw) <= _A_bound(plan, ref, dm))
+
+
 def test_satellite_long_band_pcg(gpu_lib):
     prob = synth.make_satellite(cfg_id=26, n_dets=2, samples_per_det=1 << 18, interval=1 << 17,
                                 n_rings=32, n_phi=64, lam=1 << 14, fknee=0.05, fsample=20.0)
     ref = O.plan_from_problem(prob)
     plan = _plan(gpu_lib, prob)
-    assert plan.info["fft_size"] == 65536
+    assert plan.info["fft_size"] == 65536 and plan.info["fused"] == 3
     x, info = plan.pcg_solve(_dev(prob.d[0]), tol=1e-8)
     res = O.pcg(ref, O.rhs(ref, prob.d[0]), tol=1e-8)
     err = float(_rel(x.cpu().numpy(), res.x))
