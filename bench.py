@@ -41,6 +41,11 @@ WORKLOADS = {
     "serving": "serving: 400 requests, Poisson arrivals at 0.8x the sequential capacity, Zipf(1.1) "
                "over 24 ground-like geometries (4-32 det x 2^16-2^18 samples, 32^2-128^2 patches, "
                "lambda 2^8-2^13), 1-4 RHS per request",
+    "serving_full": "serving at full ranges: Zipf(1.1) over 100 ground-like geometries of 4-128 "
+                    "det x 2^16-2^21 samples (lambda 2^8-2^13), 1-16 RHS per request, Poisson "
+                    "arrivals at 0.8x the sequential capacity; geometries are contiguous ranges of "
+                    "one 128 det x 2^21 sample stream, data white noise on the device; the first "
+                    "--requests requests of the 2,000-request trace",
     "templates": "template map-making: ground-like 256 det x 2^20 samples (268,435,456), white "
                  "noise with per-detector sigma (diagonal weights), Legendre baselines of degree "
                  "< 3 on every 8,192-sample sweep, polynomial drifts in the data",
@@ -315,15 +320,34 @@ def run_serving(args, mm, torch, dev):
 
     import synth
     t0 = time.time()
-    pool = synth.serving_pool()
-    geom, ks, gaps = synth.serving_trace()
+    full = getattr(args, "config", "") == "serving_full"
+    if full:
+        # views of one base stream: pointing slices of one device buffer, white-noise data rows
+        base, pool = synth.serving_views()
+        geom, ks, gaps = synth.serving_trace(cfg_id=6, n_requests=2000, n_geoms=len(pool),
+                                             k_range=(1, 16))
+        n_take = min(args.requests, len(geom))
+        geom, ks, gaps = geom[:n_take], ks[:n_take], gaps[:n_take]
+        bpix, bwq, bwu = (torch.from_numpy(a).to(dev) for a in (base.pix, base.wq, base.wu))
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2112033706)
+        data = torch.randn((16, base.n_samples), generator=gen, device=dev, dtype=torch.float32)
+        del base
+        dev_in = [dict(pix=bpix[v.s0:v.s0 + v.n_samples], wq=bwq[v.s0:v.s0 + v.n_samples],
+                       wu=bwu[v.s0:v.s0 + v.n_samples], d=data[:, v.s0:v.s0 + v.n_samples])
+                  for v in pool]
+    else:
+        pool = synth.serving_pool()
+        geom, ks, gaps = synth.serving_trace()
+        dev_in = []
+        for p in pool:
+            dev_in.append(dict(pix=torch.from_numpy(p.pix).to(dev),
+                               wq=torch.from_numpy(p.wq).to(dev),
+                               wu=torch.from_numpy(p.wu).to(dev), d=torch.from_numpy(p.d).to(dev)))
     n_req = len(geom)
     log(f"[bench] serving pool of {len(pool)} geometries, {n_req} requests, "
         f"generated in {time.time() - t0:.1f} s")
-    dev_in = []
-    for p in pool:
-        dev_in.append(dict(pix=torch.from_numpy(p.pix).to(dev), wq=torch.from_numpy(p.wq).to(dev),
-                           wu=torch.from_numpy(p.wu).to(dev), d=torch.from_numpy(p.d).to(dev)))
+    used = sorted(set(int(g) for g in geom))
     geoms = [mm.make_geometry(di["pix"], di["wq"], di["wu"], p.n_pix_global, p.blk_start,
                               p.blk_len, p.blk_band, p.bands, p.det_offset)
              for p, di in zip(pool, dev_in)]
@@ -332,13 +356,14 @@ def run_serving(args, mm, torch, dev):
 
     # plans once, for sizes; outputs for both runs allocated up front (inputs and outputs are
     # resident before any timed region)
-    n_kept = []
-    for gi, p in enumerate(pool):
+    n_kept = [0] * len(pool)
+    for gi in used:
+        p = pool[gi]
         with torch.cuda.stream(stream):
             pl = mm.Plan(dev_in[gi]["pix"], dev_in[gi]["wq"], dev_in[gi]["wu"], p.n_pix_global,
                          p.blk_start, p.blk_len, p.blk_band, p.bands, det_offset=p.det_offset,
                          stream=stream)
-        n_kept.append(pl.n_kept)
+        n_kept[gi] = pl.n_kept
         pl.close()
     x_seq = [torch.empty((int(ks[i]), n_kept[geom[i]], 3), dtype=torch.float64, device=dev)
              for i in range(n_req)]
@@ -423,7 +448,7 @@ def run_serving(args, mm, torch, dev):
         return done_t - t_start, lat, iters, st, samp_iters
 
     # warm-up: one pass of each geometry through both paths (plan builds, graph code paths)
-    for gi in range(len(pool)):
+    for gi in used:
         with torch.cuda.stream(stream):
             p, di = pool[gi], dev_in[gi]
             pl = mm.Plan(di["pix"], di["wq"], di["wu"], p.n_pix_global, p.blk_start, p.blk_len,
@@ -452,7 +477,7 @@ def run_serving(args, mm, torch, dev):
     n_rhs = int(ks.sum())
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not full:
         import oracle as O
         threads = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
@@ -485,7 +510,8 @@ def run_serving(args, mm, torch, dev):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 time-domain / f64 pixel-domain",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS["serving"], "requests": n_req, "rhs": n_rhs,
+        "config": {"workload": WORKLOADS["serving_full" if full else "serving"],
+                   "requests": n_req, "geometries_used": len(used), "rhs": n_rhs,
                    "tod_samples_x_rhs": work, "slots": args.slots, "load": args.load,
                    "arrival_rate_per_s": round(rate, 3), "tol": args.tol,
                    "parallelism": "single GPU"},
@@ -678,6 +704,8 @@ def main():
     ap.add_argument("--defl-m", type=int, default=64,
                     help="batched workload: Lanczos steps of the two-level preconditioner "
                          "(0: skip that comparison)")
+    ap.add_argument("--requests", type=int, default=100,
+                    help="serving_full workload: requests taken from the 2,000-request trace")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving workload: Poisson rate as a fraction of sequential capacity")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -694,7 +722,7 @@ def main():
     mm.load()
     assert torch.cuda.is_available(), "no GPU"
     dev = torch.device("cuda:0")
-    if args.config == "serving":
+    if args.config in ("serving", "serving_full"):
         print(json.dumps(run_serving(args, mm, torch, dev)), flush=True)
         return
     t0 = time.time()

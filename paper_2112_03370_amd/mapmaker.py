@@ -178,6 +178,18 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+def _data_ld(d, n=None) -> int:
+    """Leading dimension of data rows: a [k, n] view whose rows are contiguous may be strided
+    (rows of a larger buffer, ld = row stride); a 1-D vector is one row."""
+    if d.dim() == 1:
+        if d.stride(0) != 1:
+            raise ValueError("data vector must be contiguous")
+        return int(n if n is not None else d.shape[0])
+    if d.stride(-1) != 1 or d.stride(0) < d.shape[-1]:
+        raise ValueError("data rows must be contiguous, with a row stride >= their length")
+    return int(d.stride(0))
+
+
 def _host(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
@@ -315,7 +327,7 @@ class Plan:
 
     def rhs(self, d, b=None, stream=None):
         k = 1 if d.dim() == 1 else int(d.shape[0])
-        ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
+        ld = _data_ld(d, self.n_samples)
         b = b if b is not None else self._map(k)
         check(self._lib.mm_rhs(self._h, _ptr(d), k, ld, _ptr(b), _stream(stream)))
         return b
@@ -339,7 +351,7 @@ class Plan:
         enlarged-CG recurrences; < 0: group size tuned among 8, 16, 32.  refine > 0: up to that
         many FP64 refinement steps; check_fp64: report the FP64 true residual."""
         k = 1 if d.dim() == 1 else int(d.shape[0])
-        ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
+        ld = _data_ld(d, self.n_samples)
         x = x if x is not None else self._map(k)
         o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every,
                       use_graph=int(use_graph), block=int(block), precond=int(precond),
@@ -359,7 +371,7 @@ class Plan:
         """mm_pcg_solve_noalloc: PCG per column with the library's static scratch (x must be
         allocated by the caller)."""
         k = 1 if d.dim() == 1 else int(d.shape[0])
-        ld = int(d.shape[-1]) if d.dim() > 1 else self.n_samples
+        ld = _data_ld(d, self.n_samples)
         o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=int(use_x0), check_every=check_every)
         infos = (SolveInfo * max(1, k))()
         st = self._lib.mm_pcg_solve_noalloc(self._h, _ptr(d), k, ld, _ptr(x), ctypes.byref(o),
@@ -465,7 +477,7 @@ class Server:
         """Queue a solve of the rows of d (CUDA float32, [k, n] or [n]) into x (CUDA float64,
         [k, n_kept, 3] or [n_kept, 3]); returns the ticket."""
         k = 1 if d.dim() == 1 else int(d.shape[0])
-        ld = int(d.shape[-1])
+        ld = _data_ld(d)
         o = SolveOpts(tol=tol, max_iter=max_iter, use_x0=0, check_every=check_every,
                       use_graph=int(use_graph), block=int(block))
         t = ctypes.c_uint64()

@@ -16,6 +16,8 @@ from .problems import (  # noqa: F401
     make_config,
     serving_pool,
     serving_trace,
+    serving_views,
+    GeometryView,
     inverse_noise_band,
     noise_psd,
     CONFIGS,

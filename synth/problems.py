@@ -536,6 +536,63 @@ def serving_pool(cfg_id=4, n_geoms=24, dets=(4, 32), log2_samples=(16, 18), side
     return pool
 
 
+@dataclasses.dataclass
+class GeometryView:
+    """A serving geometry as a contiguous sample range [s0, s0 + n_samples) of a base stream:
+    n_dets virtual detectors of samples_per_det samples each (pieces of the base detectors),
+    stationary intervals of ``interval`` samples, its own inverse-noise bands (half-bandwidth
+    lam, the knee of the base detector each piece comes from)."""
+
+    s0: int
+    n_samples: int
+    n_dets: int
+    samples_per_det: int
+    lam: int
+    n_pix_global: int
+    blk_start: np.ndarray
+    blk_len: np.ndarray
+    blk_band: np.ndarray
+    bands: list
+    det_offset: np.ndarray
+
+
+def serving_views(cfg_id=6, n_geoms=100, dets=(4, 128), log2_samples=(16, 21),
+                  log2_lam=(8, 13), base_dets=128, base_log2=21, side=512, interval=1 << 16):
+    """Geometries of the full-range serving workload (4..128 detectors x 2^16..2^21 samples,
+    half-bandwidths 2^8..2^13) as views of one ground-like base stream of base_dets x
+    2^base_log2 samples, so that the pointing of every geometry is a slice of one device
+    buffer.  Geometry i draws detectors ~ U{dets}, samples per detector 2^e with
+    e ~ U{log2_samples}, lam = 2^g with g ~ U{log2_lam}, and a start s0 (a multiple of 2^e)
+    uniformly among those that fit.  Returns (base Problem with one data realisation, views)."""
+    base = make_ground(cfg_id=cfg_id, n_dets=base_dets, samples_per_det=1 << base_log2,
+                       interval=interval, side=side, dwell=16, lam=1 << log2_lam[1], n_rhs=1,
+                       name="serving-base")
+    fknees = np.asarray(base.meta["fknees"])
+    g = _rng(cfg_id, _S_TRACE, 2)
+    n_base = base.n_samples
+    cache = {}
+    views = []
+    for _ in range(n_geoms):
+        nd = int(g.integers(dets[0], dets[1] + 1))
+        e = int(g.integers(log2_samples[0], log2_samples[1] + 1))
+        lam = 1 << int(g.integers(log2_lam[0], log2_lam[1] + 1))
+        per = 1 << e
+        n = nd * per
+        s0 = per * int(g.integers(0, (n_base - n) // per + 1))
+        bands = []
+        for i in range(nd):
+            fk = round(float(fknees[(s0 + i * per) >> base_log2]), 1)
+            key = (fk, lam)
+            if key not in cache:
+                cache[key] = inverse_noise_band(lam, base.meta["fsample"], 1.0, fk, -1.0)
+            bands.append(cache[key])
+        det_offset = np.arange(nd + 1, dtype=np.int64) * per
+        bs, bl, bb = _blocks_for(det_offset, interval, list(range(nd)))
+        views.append(GeometryView(s0, n, nd, per, lam, base.n_pix_global, bs, bl, bb, bands,
+                                  det_offset))
+    return base, views
+
+
 def serving_trace(cfg_id=4, n_requests=400, n_geoms=24, zipf_s=1.1, k_range=(1, 4)):
     """Request trace: geometry index by Zipf(zipf_s) popularity over the pool, right-hand sides
     per request ~ U{k_range}, and unit-rate exponential inter-arrival gaps (Poisson arrivals;

@@ -56,3 +56,22 @@ def test_white_band_is_delta_and_bands_have_positive_symbol():
         h[1:c.size] = c[1:]
         h[n - c.size + 1:] = c[1:][::-1]
         assert np.fft.rfft(h).real.min() > 0
+
+
+def test_serving_views_are_slices_of_the_base_stream():
+    base, views = synth.serving_views(cfg_id=7, n_geoms=12, dets=(2, 8), log2_samples=(12, 14),
+                                      log2_lam=(4, 6), base_dets=8, base_log2=14, side=32,
+                                      interval=1 << 12)
+    assert base.n_samples == 8 << 14
+    for v in views:
+        per = v.samples_per_det
+        assert 2 <= v.n_dets <= 8 and per in (1 << 12, 1 << 13, 1 << 14)
+        assert v.s0 % per == 0 and v.s0 + v.n_samples <= base.n_samples
+        assert v.n_samples == v.n_dets * per and v.det_offset[-1] == v.n_samples
+        # every piece lies inside one base detector, so its intervals are base intervals
+        assert all(((v.s0 + i * per) >> 14) == ((v.s0 + (i + 1) * per - 1) >> 14)
+                   for i in range(v.n_dets))
+        assert np.array_equal(np.diff(v.det_offset), np.full(v.n_dets, per))
+        assert v.blk_len.sum() == v.n_samples and np.all(v.blk_start % (1 << 12) == 0)
+        assert len(v.bands) == v.n_dets and v.blk_band.max() == v.n_dets - 1
+        assert all(len(b) == v.lam + 1 for b in v.bands) and v.lam in (16, 32, 64)
