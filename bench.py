@@ -399,8 +399,8 @@ def run_serving(args, mm, torch, dev):
             pl.close()
         return total, np.array(lat), iters
 
-    def served(arrivals, n_slots):
-        srv = mm.Server(n_slots=n_slots)
+    def served(arrivals, n_slots, large_work=0):
+        srv = mm.Server(n_slots=n_slots, large_work=large_work, large_slots=args.large_slots)
         t_arr = np.zeros(n_req)
         t_sub = np.zeros(n_req)
         tickets = [None] * n_req
@@ -460,20 +460,28 @@ def run_serving(args, mm, torch, dev):
     t_seq, lat_seq_sat, it_seq = sequential(None)
     cap_seq = n_req / t_seq
     log(f"[bench] sequential, saturated: {t_seq:.2f} s, {cap_seq:.1f} requests/s")
-    t_srv, lat_srv_sat, it_srv, st_sat, samp_srv = served(None, args.slots)
-    log(f"[bench] served ({args.slots} slots), saturated: {t_srv:.2f} s, "
-        f"{n_req / t_srv:.1f} requests/s, peak running {st_sat['peak_running']}")
+    t_srv, lat_srv_sat, it_srv, st_sat, samp_srv = served(None, args.slots, args.large_work)
+    log(f"[bench] served ({args.slots} slots, large from {args.large_work} sample-RHS at most "
+        f"{args.large_slots} at once), saturated: {t_srv:.2f} s, {n_req / t_srv:.1f} requests/s, "
+        f"peak running {st_sat['peak_running']}, peak large {st_sat['peak_large']}")
     # same results alone and in the mix
     diffs = [float((a - b).norm() / b.norm().clamp_min(1e-300)) for a, b in zip(x_srv, x_seq)]
     max_diff = max(diffs)
     rate = args.load * cap_seq
     arrivals = np.cumsum(gaps) / rate
     t_seq_p, lat_seq, _ = sequential(arrivals)
-    t_srv_p, lat_srv, _, st_p, _ = served(arrivals, args.slots)
+    t_srv_p, lat_srv, _, st_p, _ = served(arrivals, args.slots, args.large_work)
     pct = lambda a, q: round(float(np.percentile(a, q)), 3)  # noqa: E731
     log(f"[bench] Poisson at {rate:.1f} requests/s: sequential p50 {pct(lat_seq, 50)} ms p99 "
         f"{pct(lat_seq, 99)} ms; served p50 {pct(lat_srv, 50)} ms p99 {pct(lat_srv, 99)} ms; "
         f"max map rel diff mix vs alone {max_diff:.2e}")
+    fifo = None
+    if full and args.large_work > 0:
+        # the same arrivals served without size classes (one class, first come first served)
+        _, lat_fifo, _, _, _ = served(arrivals, args.slots, 0)
+        fifo = {"p50_ms": pct(lat_fifo, 50), "p99_ms": pct(lat_fifo, 99)}
+        log(f"[bench] Poisson, served without size classes: p50 {fifo['p50_ms']} ms p99 "
+            f"{fifo['p99_ms']} ms")
     n_rhs = int(ks.sum())
 
     cpu = None
@@ -518,12 +526,15 @@ def run_serving(args, mm, torch, dev):
         "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99),
                    "saturated_requests_per_s": round(n_req / t_srv, 3),
                    "saturated_rhs_solves_per_s": round(n_rhs / t_srv, 3),
-                   "peak_running": st_sat["peak_running"], "plan_hits": st_p["plan_hits"],
+                   "peak_running": st_sat["peak_running"], "peak_large": st_sat["peak_large"],
+                   "large_work": args.large_work, "large_slots": args.large_slots,
+                   "plan_hits": st_p["plan_hits"],
                    "plan_misses": st_p["plan_misses"],
                    "peak_device_bytes": st_sat["peak_bytes"]},
         "sequential": {"p50_ms": pct(lat_seq, 50), "p99_ms": pct(lat_seq, 99),
                        "saturated_requests_per_s": round(cap_seq, 3),
                        "saturated_rhs_solves_per_s": round(n_rhs / t_seq, 3)},
+        "served_one_class": fifo,
         "speedup_saturated": round(t_seq / t_srv, 3),
         "max_map_rel_diff_mix_vs_alone": max_diff,
         "iterations_total": int(it_srv),
@@ -704,6 +715,11 @@ def main():
     ap.add_argument("--defl-m", type=int, default=64,
                     help="batched workload: Lanczos steps of the two-level preconditioner "
                          "(0: skip that comparison)")
+    ap.add_argument("--large-work", type=int, default=1 << 26,
+                    help="serving workloads: requests of samples x RHS from this size are large "
+                         "(0: one class)")
+    ap.add_argument("--large-slots", type=int, default=1,
+                    help="serving workloads: large requests running at once")
     ap.add_argument("--requests", type=int, default=100,
                     help="serving_full workload: requests taken from the 2,000-request trace")
     ap.add_argument("--load", type=float, default=0.8,

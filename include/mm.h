@@ -331,12 +331,21 @@ mm_status mm_kernel_time(mm_plan_t* plan, int32_t kind, double* total_ms, int64_
  * for reuse and released, then unpinned plans evicted least recently used first, when memory is
  * needed.  Each request runs exactly the computation of mm_pcg_solve on its own (its columns
  * never share a block with another request's), so its result does not depend on the mix apart
- * from the order of FP64 atomic additions. */
+ * from the order of FP64 atomic additions.  With size classes (large_work > 0), requests whose
+ * work n_samples x k reaches large_work run at most large_slots at a time: on a saturated
+ * device concurrency only divides a large solve's share, so large requests keep close to their
+ * run-alone time while small ones flow past them on the other slots. */
 typedef struct {
   int64_t hbm_budget;    /* device bytes for cached plans + request workspaces; <= 0: 80% of
                             the free device memory at creation */
   int32_t n_slots;       /* solves running at once; <= 0: 4 */
   int32_t max_bypass;    /* later requests that may start before a waiting one; < 0: 16 */
+  int64_t large_work;    /* size classes: a request of n_samples x k >= large_work is large;
+                            <= 0: one class (no size rule) */
+  int32_t large_slots;   /* large requests running at once (<= 0: 1); small requests take the
+                            other slots, and a large request held by this rule lets later
+                            requests pass without counting as bypassed */
+  int32_t pad0;
 } mm_server_opts;
 
 typedef struct {
@@ -360,6 +369,8 @@ typedef struct {
   int32_t running;
   int32_t peak_running;  /* most requests that ran at once */
   int32_t n_plans;
+  int32_t peak_large;    /* most large requests that ran at once */
+  int32_t pad0;
 } mm_server_stats_t;
 
 /* Create a server on the current device.  opts may be NULL (defaults).  Errors: MM_ERR_INVALID,

@@ -7,6 +7,8 @@
 // own, so the kernels of several requests overlap on the device and a request that arrives
 // while others run starts as soon as a slot and memory are free.  A request that does not fit
 // lets later ones pass, at most max_bypass times, so that large requests are not starved.
+// With size classes, requests whose work (samples x right-hand sides) reaches large_work run at
+// most large_slots at a time; small requests pass a held large one freely.
 // Idle workspaces stay with their plan for reuse; under memory pressure idle workspaces are
 // released first, then unpinned plans, least recently used first.
 #include <chrono>
@@ -44,6 +46,7 @@ struct Request {
   mm_solve_opts opts{};
   int64_t extra_bytes = 0;     // block-solve workspace on top of a solve workspace
   int32_t bypassed = 0;
+  bool large = false;          // size class (n_samples x k >= the server's large_work)
   Clock::time_point t_submit, t_start, t_end;
   bool done = false;
   mm_status status = MM_PENDING;
@@ -61,6 +64,10 @@ struct Server {
   int64_t budget = 0;
   int32_t n_slots = 4;
   int32_t max_bypass = 16;
+  int64_t large_work = 0;    // size classes: work n_samples x k at which a request is large
+  int32_t large_slots = 1;   // large requests running at once
+  int32_t running_large = 0;
+  int32_t peak_large = 0;
   std::mutex mu;
   std::condition_variable cv_work;   // workers: admissible request or stop
   std::condition_variable cv_state;  // plan builds finished, requests finished
@@ -164,10 +171,14 @@ Request* pick_locked(Server* S) {
 Request* try_admit_locked(Server* S) {
   for (size_t i = 0; i < S->queue.size(); ++i) {
     Request* r = S->queue[i];
+    // a large request held by the size rule does not block later (small) ones
+    if (r->large && S->running_large >= S->large_slots) continue;
     const int64_t cost = admission_cost(r);
     if (S->in_use + cost > S->budget) reclaim_locked(S, cost);
     if (S->in_use + cost <= S->budget) {
-      for (size_t j = 0; j < i; ++j) S->queue[j]->bypassed += 1;
+      for (size_t j = 0; j < i; ++j)
+        if (!(S->queue[j]->large && S->running_large >= S->large_slots))
+          S->queue[j]->bypassed += 1;
       S->queue.erase(S->queue.begin() + static_cast<std::ptrdiff_t>(i));
       CacheEntry* e = r->entry;
       if (e->own_work_free) {
@@ -267,6 +278,7 @@ void finish_request_locked(Server* S, Request* r, mm_status st) noexcept {
   r->t_end = Clock::now();
   r->done = true;
   S->running -= 1;
+  if (r->large) S->running_large -= 1;
   S->completed += 1;
 }
 
@@ -287,6 +299,10 @@ void worker_loop(Server* S, int slot) {
       r->t_start = Clock::now();
       S->running += 1;
       S->peak_running = std::max(S->peak_running, S->running);
+      if (r->large) {
+        S->running_large += 1;
+        S->peak_large = std::max(S->peak_large, S->running_large);
+      }
     }
     const mm_status st = serve_request(S, r, s);
     {
@@ -368,6 +384,8 @@ mm_status mm_server_create(const mm_server_opts* opts, mm_server_t** out) {
     S->n_slots = o.n_slots > 0 ? o.n_slots : 4;
     if (S->n_slots > 64) return fail(MM_ERR_INVALID, "n_slots > 64");
     S->max_bypass = o.max_bypass >= 0 ? o.max_bypass : 16;
+    S->large_work = o.large_work > 0 ? o.large_work : 0;
+    S->large_slots = o.large_slots > 0 ? o.large_slots : 1;
     if (o.hbm_budget > 0) {
       S->budget = o.hbm_budget;
     } else {
@@ -557,6 +575,7 @@ mm_status mm_submit(mm_server_t* server, uint64_t key, const float* d, int32_t k
     r->x = x;
     if (opts) r->opts = *opts;
     r->extra_bytes = block_extra_bytes(P, r->opts, k);
+    r->large = S->large_work > 0 && P->n_samples * static_cast<int64_t>(k) >= S->large_work;
     // the plan's own workspace is always there once free: only the block extra must fit
     if (e->plan_bytes + r->extra_bytes > S->budget)
       return fail(MM_ERR_BUDGET, "request can never fit the memory budget");
@@ -626,6 +645,7 @@ mm_status mm_server_stats(mm_server_t* server, mm_server_stats_t* out) {
   out->queued = static_cast<int32_t>(S->queue.size());
   out->running = S->running;
   out->peak_running = S->peak_running;
+  out->peak_large = S->peak_large;
   out->n_plans = static_cast<int32_t>(S->cache.size());
   return MM_OK;
 }

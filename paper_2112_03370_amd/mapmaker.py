@@ -86,7 +86,8 @@ class DeflationInfo(ctypes.Structure):
 
 
 class ServerOpts(ctypes.Structure):
-    _fields_ = [("hbm_budget", _c_i64), ("n_slots", _c_i32), ("max_bypass", _c_i32)]
+    _fields_ = [("hbm_budget", _c_i64), ("n_slots", _c_i32), ("max_bypass", _c_i32),
+                ("large_work", _c_i64), ("large_slots", _c_i32), ("pad0", _c_i32)]
 
 
 class RequestTimes(ctypes.Structure):
@@ -101,10 +102,11 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("hbm_budget", _c_i64), ("bytes_in_use", _c_i64), ("peak_bytes", _c_i64),
                 ("submitted", _c_i64), ("completed", _c_i64), ("plan_hits", _c_i64),
                 ("plan_misses", _c_i64), ("evictions", _c_i64), ("queued", _c_i32),
-                ("running", _c_i32), ("peak_running", _c_i32), ("n_plans", _c_i32)]
+                ("running", _c_i32), ("peak_running", _c_i32), ("n_plans", _c_i32),
+                ("peak_large", _c_i32), ("pad0", _c_i32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
 
 
 _lib = None
@@ -436,10 +438,13 @@ def exported_symbols(header: Optional[str] = None) -> Sequence[str]:
 class Server:
     """Serving loop: device-cached plans and continuously batched solves (mm_server_*)."""
 
-    def __init__(self, hbm_budget=0, n_slots=4, max_bypass=-1):
+    def __init__(self, hbm_budget=0, n_slots=4, max_bypass=-1, large_work=0, large_slots=1):
+        """large_work > 0: requests of n_samples x k >= large_work run at most large_slots at
+        a time (size classes)."""
         self._lib = load()
         o = ServerOpts(hbm_budget=int(hbm_budget), n_slots=int(n_slots),
-                       max_bypass=int(max_bypass))
+                       max_bypass=int(max_bypass), large_work=int(large_work),
+                       large_slots=int(large_slots))
         h = _vp()
         self._h = None
         check(self._lib.mm_server_create(ctypes.byref(o), ctypes.byref(h)))

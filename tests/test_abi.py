@@ -68,7 +68,8 @@ int main(void) {
   printf("mm_request_times %zu\n", sizeof(mm_request_times));
   printf("mm_server_stats_t %zu\n", sizeof(mm_server_stats_t));
   P(mm_server_opts, max_bypass) P(mm_request_times, slot) P(mm_server_stats_t, queued)
-  P(mm_server_stats_t, n_plans)
+  P(mm_server_stats_t, n_plans) P(mm_server_opts, large_work) P(mm_server_opts, large_slots)
+  P(mm_server_stats_t, peak_large)
   printf("mm_deflation_info_t %zu\n", sizeof(mm_deflation_info_t));
   P(mm_deflation_info_t, build_ms) P(mm_deflation_info_t, device_bytes) P(mm_solve_opts, precond)
   P(mm_geometry, precision) P(mm_geometry, n_poly) P(mm_geometry, n_baselines)
@@ -110,6 +111,9 @@ int main(void) {
         "mm_request_times.slot": M.RequestTimes.slot.offset,
         "mm_server_stats_t.queued": M.ServerStats.queued.offset,
         "mm_server_stats_t.n_plans": M.ServerStats.n_plans.offset,
+        "mm_server_opts.large_work": M.ServerOpts.large_work.offset,
+        "mm_server_opts.large_slots": M.ServerOpts.large_slots.offset,
+        "mm_server_stats_t.peak_large": M.ServerStats.peak_large.offset,
         "mm_deflation_info_t": ctypes.sizeof(M.DeflationInfo),
         "mm_deflation_info_t.build_ms": M.DeflationInfo.build_ms.offset,
         "mm_deflation_info_t.device_bytes": M.DeflationInfo.device_bytes.offset,

@@ -94,6 +94,34 @@ def test_requests_in_the_mix_match_alone_and_oracle(gpu_lib):
             assert err <= 1e-6, (i, j, err)
 
 
+def test_size_classes_hold_large_requests_to_their_slots(gpu_lib):
+    # work n_samples x k: the 4-detector raster (3 RHS) and the ground case (2 RHS) are large
+    import torch
+    probs = problems()
+    alone = [_alone(gpu_lib, p) for p in probs]
+    work = [p.n_samples * p.d.shape[0] for p in probs]
+    large_work = 50000
+    assert [w >= large_work for w in work] == [False, True, False, True, False], work
+    srv = gpu_lib.Server(n_slots=4, large_work=large_work, large_slots=1)
+    infos = [srv.plan_from_problem(200 + i, p) for i, p in enumerate(probs)]
+    tickets = []
+    for rep in range(3):
+        for i, p in enumerate(probs):
+            x = torch.empty((p.d.shape[0], infos[i]["n_kept"], 3), dtype=torch.float64,
+                            device="cuda")
+            tickets.append((i, srv.submit(200 + i, _dev(p.d), x, tol=1e-8)))
+    for i, t in tickets:
+        res = srv.wait(t)
+        assert res["status"] == "MM_OK"
+        err = float(_rel(res["x"].cpu().numpy().reshape(alone[i].shape), alone[i]))
+        assert err <= 1e-8, (i, err)
+    st = srv.stats()
+    assert st["completed"] == len(tickets) and st["queued"] == 0
+    assert st["peak_large"] == 1, st
+    assert st["peak_running"] >= 2, st
+    srv.close()
+
+
 def test_budget_admission_serializes_requests_of_one_plan(gpu_lib):
     import torch
     p = problems()[1]
