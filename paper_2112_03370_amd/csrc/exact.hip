@@ -431,48 +431,133 @@ __device__ __forceinline__ void xfft(double2 (&v)[16], double* sh, int t, bool p
   xpass<4, T>(v, t, 16 * R2 * R3, paired_last, tw);
 }
 
+// FP64 samples of one lane of 8 consecutive window samples [g, g + 8), all inside the block and
+// g a multiple of 4: the pointing comes in 16-byte loads, and scan runs keep a pixel for several
+// samples, so the pixel values of the lane's first and last samples are loaded together and a
+// third pixel only when one occurs.  The sums are those of the one-sample form.
+template <bool kData>
+__device__ __forceinline__ void xgather8(const int32_t* __restrict__ lpix,
+                                         const float* __restrict__ wq,
+                                         const float* __restrict__ wu,
+                                         const double* __restrict__ x,
+                                         const float* __restrict__ d, int64_t g,
+                                         double (&o)[8]) {
+  int kk[8];
+  float qq[8], uu[8];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int4 k4 = *reinterpret_cast<const int4*>(lpix + g + 4 * c);
+    kk[4 * c] = k4.x;
+    kk[4 * c + 1] = k4.y;
+    kk[4 * c + 2] = k4.z;
+    kk[4 * c + 3] = k4.w;
+    const float4 q4 = *reinterpret_cast<const float4*>((kData ? d : wq) + g + 4 * c);
+    qq[4 * c] = q4.x;
+    qq[4 * c + 1] = q4.y;
+    qq[4 * c + 2] = q4.z;
+    qq[4 * c + 3] = q4.w;
+    if constexpr (!kData) {
+      const float4 u4 = *reinterpret_cast<const float4*>(wu + g + 4 * c);
+      uu[4 * c] = u4.x;
+      uu[4 * c + 1] = u4.y;
+      uu[4 * c + 2] = u4.z;
+      uu[4 * c + 3] = u4.w;
+    }
+  }
+  if constexpr (kData) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = kk[j] < 0 ? 0.0 : static_cast<double>(qq[j]);
+  } else {
+    const int ka = kk[0], kb = kk[7];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    if (ka >= 0) {
+      const double* m = x + 3 * static_cast<int64_t>(ka);
+      a0 = m[0];
+      a1 = m[1];
+      a2 = m[2];
+    }
+    if (kb >= 0 && kb != ka) {
+      const double* m = x + 3 * static_cast<int64_t>(kb);
+      b0 = m[0];
+      b1 = m[1];
+      b2 = m[2];
+    }
+    bool other = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int key = kk[j];
+      other |= key >= 0 && key != ka && key != kb;
+      const double q = static_cast<double>(qq[j]), u = static_cast<double>(uu[j]);
+      const double ta = a0 + q * a1 + u * a2;
+      const double tb = b0 + q * b1 + u * b2;
+      o[j] = key < 0 ? 0.0 : (key == ka ? ta : tb);
+    }
+    if (other) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int key = kk[j];
+        if (key >= 0 && key != ka && key != kb) {
+          const double* m = x + 3 * static_cast<int64_t>(key);
+          o[j] = m[0] + static_cast<double>(qq[j]) * m[1] + static_cast<double>(uu[j]) * m[2];
+        }
+      }
+    }
+  }
+}
+
 template <int M, bool kData>
 __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
-    const double* __restrict__ x, const float* __restrict__ d, const Chunk* __restrict__ chunks,
-    int lam, const double* __restrict__ spec, const double2* __restrict__ tw0, double inv_n,
-    double* __restrict__ y) {
+    const double* __restrict__ x, const float* __restrict__ d, int dvec,
+    const Chunk* __restrict__ chunks, int lam, const double* __restrict__ spec,
+    const double2* __restrict__ tw0, double inv_n, double* __restrict__ y) {
   using C = XFused<M>;
   constexpr int NC = C::NC, T = C::T, PL = NC / 4;
   static_assert(C::R2 * C::R3 * 16 * 4 == NC, "pass radices");
-  __shared__ double sh[C::LDS + 32];
+  __shared__ __align__(16) double sh[C::LDS + 32];
   const Chunk c = chunks[blockIdx.x];
   const int t = threadIdx.x;
   const int64_t b0 = c.blk_start, b1 = c.blk_start + c.blk_len;
 
   // ---- window samples, packed as complex points at the first pass's slots ------------------
-  // staged through LDS one component at a time (even samples, then odd ones): a plain loop
-  // keeps the gather's loads from all being in flight at once
+  // Two halves of NC samples (NC / 2 points) staged through LDS, where sample n of a half sits
+  // at n (point p at 2p and 2p + 1); lanes take 8 consecutive samples (two rounds per half)
   double2 v[16];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    for (int n = t; n < NC; n += T) {
-      const int64_t g = c.out0 - lam + 2 * static_cast<int64_t>(n) + h;
-      double val = 0.0;
-      if (g >= b0 && g < b1) {
-        const int p = lpix[g];
-        if (p >= 0) {
-          if (kData) {
-            val = static_cast<double>(d[g]);
-          } else {
-            const double* m = x + 3 * static_cast<int64_t>(p);
-            val = m[0] + static_cast<double>(wq[g]) * m[1] + static_cast<double>(wu[g]) * m[2];
+#pragma unroll 1
+    for (int r = 0; r < 2; ++r) {
+      const int n = 8 * (t + r * T);  // sample of the half
+      const int64_t g = c.out0 - lam + static_cast<int64_t>(h) * NC + n;
+      double o[8];
+      if (g >= b0 && g + 8 <= b1 && (g & 3) == 0 && (!kData || dvec)) {
+        xgather8<kData>(lpix, wq, wu, x, d, g, o);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t gj = g + j;
+          double val = 0.0;
+          if (gj >= b0 && gj < b1) {
+            const int p = lpix[gj];
+            if (p >= 0) {
+              if (kData) {
+                val = static_cast<double>(d[gj]);
+              } else {
+                const double* m = x + 3 * static_cast<int64_t>(p);
+                val = m[0] + static_cast<double>(wq[gj]) * m[1] + static_cast<double>(wu[gj]) * m[2];
+              }
+            }
           }
+          o[j] = val;
         }
       }
-      sh[xpad(n)] = val;
+      double2* dst = reinterpret_cast<double2*>(sh + n);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[j] = make_double2(o[2 * j], o[2 * j + 1]);
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double val = sh[xpad(t + j * T)];
-      if (h) v[j].y = val; else v[j].x = val;
-    }
+    for (int j = 0; j < 8; ++j) v[8 * h + j] = reinterpret_cast<const double2*>(sh)[t + j * T];
     __syncthreads();
   }
 
@@ -563,39 +648,75 @@ __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
     if (o0 + 1 >= 0 && o0 + 1 < c.out_len) sh[xpad(o0 + 1)] = -v[s].y * inv_n;
   }
   __syncthreads();
-  for (int o0 = 4 * t; o0 - 4 * t < c.out_len; o0 += 4 * T) {
-    int key[4];
-    double vv[4][3];
+  for (int base = 0; base < c.out_len; base += 8 * T) {  // same trip count for every lane
+    const int i0 = base + 8 * t;
+    const int64_t o = c.out0 + i0;
+    int key[8];
+    double vv[8][3];
+    if (i0 + 8 <= c.out_len && (o & 3) == 0) {
+      int kk[8];
+      float qq[8], uu[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int o = o0 + i;
-      key[i] = -1;
-      vv[i][0] = vv[i][1] = vv[i][2] = 0.0;
-      if (o < c.out_len) {
-        const int64_t g = c.out0 + o;
-        const int p = lpix[g];
-        if (p >= 0) {
-          const double u = sh[xpad(o)];
-          key[i] = p;
-          vv[i][0] = u;
-          vv[i][1] = static_cast<double>(wq[g]) * u;
-          vv[i][2] = static_cast<double>(wu[g]) * u;
+      for (int q = 0; q < 2; ++q) {
+        const int4 k4 = *reinterpret_cast<const int4*>(lpix + o + 4 * q);
+        const float4 q4 = *reinterpret_cast<const float4*>(wq + o + 4 * q);
+        const float4 u4 = *reinterpret_cast<const float4*>(wu + o + 4 * q);
+        kk[4 * q] = k4.x;
+        kk[4 * q + 1] = k4.y;
+        kk[4 * q + 2] = k4.z;
+        kk[4 * q + 3] = k4.w;
+        qq[4 * q] = q4.x;
+        qq[4 * q + 1] = q4.y;
+        qq[4 * q + 2] = q4.z;
+        qq[4 * q + 3] = q4.w;
+        uu[4 * q] = u4.x;
+        uu[4 * q + 1] = u4.y;
+        uu[4 * q + 2] = u4.z;
+        uu[4 * q + 3] = u4.w;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double u = sh[xpad(i0 + i)];
+        key[i] = kk[i];
+        vv[i][0] = u;
+        vv[i][1] = static_cast<double>(qq[i]) * u;
+        vv[i][2] = static_cast<double>(uu[i]) * u;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int oi = i0 + i;
+        key[i] = -1;
+        vv[i][0] = vv[i][1] = vv[i][2] = 0.0;
+        if (oi < c.out_len) {
+          const int64_t g = c.out0 + oi;
+          const int p = lpix[g];
+          if (p >= 0) {
+            const double u = sh[xpad(oi)];
+            key[i] = p;
+            vv[i][0] = u;
+            vv[i][1] = static_cast<double>(wq[g]) * u;
+            vv[i][2] = static_cast<double>(wu[g]) * u;
+          }
         }
       }
     }
-    wave_merge_runs<3>(key, vv, XFlush{y});
+    wave_merge_runs_n<8, 3>(key, vv, XFlush{y});
   }
 }
 
 template <int M>
 mm_status launch_fused_m(Plan* P, const double* x, const float* d, double* y, hipStream_t s) {
   const double inv_n = 1.0 / static_cast<double>(P->fft_n);
+  const int dvec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 ? 1 : 0;
   if (x == nullptr)
     hipLaunchKernelGGL((k_x_fused<M, true>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s, P->lpix,
-                       P->wq, P->wu, x, d, P->chunks, P->lambda_max, P->x_spec, P->x_tw, inv_n, y);
+                       P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec, P->x_tw,
+                       inv_n, y);
   else
     hipLaunchKernelGGL((k_x_fused<M, false>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s, P->lpix,
-                       P->wq, P->wu, x, d, P->chunks, P->lambda_max, P->x_spec, P->x_tw, inv_n, y);
+                       P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec, P->x_tw,
+                       inv_n, y);
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
 }
