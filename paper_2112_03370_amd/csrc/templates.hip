@@ -66,6 +66,11 @@ __device__ __forceinline__ void legendre(double x, const double* scale, double (
   }
 }
 
+// Samples j0 .. j0 + 3 of a baseline: pixel, weights and t = (P x)_s (or the data sample) in
+// FP64; key -1 for gap samples and samples past the end.  A lane whose 4 samples lie inside the
+// baseline at a 16-byte boundary loads its pointing with 16-byte loads, and since scan runs keep
+// a pixel for several samples, it loads the pixel values of its first and last samples once
+// each and a third pixel only when one occurs.  The sums are those of the one-sample form.
 template <bool kData>
 __device__ __forceinline__ void load4(const int32_t* __restrict__ lpix,
                                       const float* __restrict__ wq,
@@ -74,6 +79,69 @@ __device__ __forceinline__ void load4(const int32_t* __restrict__ lpix,
                                       const float* __restrict__ d, int64_t start, int len,
                                       int j0, int (&key)[4], double (&t)[4], float (&q)[4],
                                       float (&u)[4]) {
+  const int64_t g0 = start + j0;
+  const bool vec = j0 + 4 <= len && (g0 & 3) == 0 &&
+                   (!kData || (reinterpret_cast<uintptr_t>(d + g0) & 15u) == 0);
+  if (vec) {
+    const int4 k4 = *reinterpret_cast<const int4*>(lpix + g0);
+    const float4 q4 = *reinterpret_cast<const float4*>(wq + g0);
+    const float4 u4 = *reinterpret_cast<const float4*>(wu + g0);
+    key[0] = k4.x;
+    key[1] = k4.y;
+    key[2] = k4.z;
+    key[3] = k4.w;
+    q[0] = q4.x;
+    q[1] = q4.y;
+    q[2] = q4.z;
+    q[3] = q4.w;
+    u[0] = u4.x;
+    u[1] = u4.y;
+    u[2] = u4.z;
+    u[3] = u4.w;
+    if constexpr (kData) {
+      const float4 d4 = *reinterpret_cast<const float4*>(d + g0);
+      t[0] = key[0] < 0 ? 0.0 : static_cast<double>(d4.x);
+      t[1] = key[1] < 0 ? 0.0 : static_cast<double>(d4.y);
+      t[2] = key[2] < 0 ? 0.0 : static_cast<double>(d4.z);
+      t[3] = key[3] < 0 ? 0.0 : static_cast<double>(d4.w);
+    } else {
+      const int ka = key[0], kb = key[3];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+      if (ka >= 0) {
+        const double* m = x + 3 * static_cast<int64_t>(ka);
+        a0 = m[0];
+        a1 = m[1];
+        a2 = m[2];
+      }
+      if (kb >= 0 && kb != ka) {
+        const double* m = x + 3 * static_cast<int64_t>(kb);
+        b0 = m[0];
+        b1 = m[1];
+        b2 = m[2];
+      }
+      bool other = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = key[i];
+        other |= k >= 0 && k != ka && k != kb;
+        const double qd = static_cast<double>(q[i]), ud = static_cast<double>(u[i]);
+        const double ta = a0 + qd * a1 + ud * a2;
+        const double tb = b0 + qd * b1 + ud * b2;
+        t[i] = k < 0 ? 0.0 : (k == ka ? ta : tb);
+      }
+      if (other) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = key[i];
+          if (k >= 0 && k != ka && k != kb) {
+            const double* m = x + 3 * static_cast<int64_t>(k);
+            t[i] = m[0] + static_cast<double>(q[i]) * m[1] + static_cast<double>(u[i]) * m[2];
+          }
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int j = j0 + i;
