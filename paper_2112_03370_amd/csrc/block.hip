@@ -34,68 +34,58 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxT = 32;
-constexpr int kTileRows = 64;
 
-// partial[wg][i * tv + j] = sum over the workgroup's rows of U_i[r] V_j[r].  With few pairs
-// (t x t <= 128) each pair gets tpp threads, each summing every tpp-th row of a tile, and a
-// fixed tree over them at the end; with more, a thread sums whole tiles for up to 4 pairs.
-__global__ __launch_bounds__(kThreads) void k_gram(const double* __restrict__ U, int tu,
-                                                   int64_t ldu, const double* __restrict__ V,
-                                                   int tv, int64_t ldv, int64_t n,
-                                                   double* __restrict__ partial) {
-  __shared__ double su[kMaxT][kTileRows + 1];
-  __shared__ double sv[kMaxT][kTileRows + 1];
-  __shared__ double red[kThreads];
-  const int npair = tu * tv;
-  const int ncol = tu > tv ? tu : tv;
-  int tpp = 1;  // threads per pair (power of two)
-  while (tpp < kTileRows && 2 * tpp * npair <= kThreads) tpp *= 2;
-  const int p0 = threadIdx.x / tpp, sub = threadIdx.x % tpp;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * kTileRows; r0 < n;
-       r0 += static_cast<int64_t>(gridDim.x) * kTileRows) {
-    for (int e = threadIdx.x; e < ncol * kTileRows; e += kThreads) {
-      const int col = e / kTileRows, row = e % kTileRows;
-      const int64_t r = r0 + row;
-      su[col][row] = (col < tu && r < n) ? U[col * ldu + r] : 0.0;
-      sv[col][row] = (col < tv && r < n) ? V[col * ldv + r] : 0.0;
-    }
-    __syncthreads();
-    if (tpp > 1) {
-      if (p0 < npair) {
-        const int i = p0 / tv, j = p0 % tv;
-        double s = 0.0;
-        for (int row = sub; row < kTileRows; row += tpp) s += su[i][row] * sv[j][row];
-        acc[0] += s;
-      }
-    } else {
+// Gram partials partial[x][i * tv + j] = sum over workgroup x's rows of U_i[r] V_j[r], streamed:
+// workgroup (x, y) takes the 8 x 8 block y of column pairs and
+// a grid-stride share of the rows; each thread keeps its 64 pair sums in registers over all its
+// rows (8 + 8 coalesced loads and 64 FMAs per row, no barrier in the loop), then the workgroup
+// reduces them once (wavefront shuffles, then LDS across the 4 wavefronts) in a fixed order.
+// (A tiled form that staged 64-row tiles of U and V in LDS waited on memory at every tile and
+// took ~160 us per call for t = 8.)
+constexpr int kGB = 8;
+
+__global__ __launch_bounds__(kThreads) void k_gram_rb(const double* __restrict__ U, int tu,
+                                                      int64_t ldu, const double* __restrict__ V,
+                                                      int tv, int64_t ldv, int64_t n,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64][kGB * kGB];
+  const int nbv = (tv + kGB - 1) / kGB;
+  const int i0 = (blockIdx.y / nbv) * kGB, j0 = (blockIdx.y % nbv) * kGB;
+  const int nu = min(kGB, tu - i0), nv = min(kGB, tv - j0);
+  double acc[kGB][kGB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int pidx = threadIdx.x + q * kThreads;
-        if (pidx < npair) {
-          const int i = pidx / tv, j = pidx % tv;
-          double s = 0.0;
-          for (int row = 0; row < kTileRows; ++row) s += su[i][row] * sv[j][row];
-          acc[q] += s;
-        }
-      }
-    }
-    __syncthreads();
+  for (int a = 0; a < kGB; ++a)
+#pragma unroll
+    for (int b = 0; b < kGB; ++b) acc[a][b] = 0.0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; r < n;
+       r += static_cast<int64_t>(gridDim.x) * kThreads) {
+    double u[kGB], v[kGB];
+#pragma unroll
+    for (int a = 0; a < kGB; ++a) u[a] = a < nu ? U[(i0 + a) * ldu + r] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kGB; ++b) v[b] = b < nv ? V[(j0 + b) * ldv + r] : 0.0;
+#pragma unroll
+    for (int a = 0; a < kGB; ++a)
+#pragma unroll
+      for (int b = 0; b < kGB; ++b) acc[a][b] = fma(u[a], v[b], acc[a][b]);
   }
-  if (tpp > 1) {
-    red[threadIdx.x] = acc[0];
-    __syncthreads();
-    for (int h = tpp / 2; h > 0; h >>= 1) {
-      if (sub < h) red[threadIdx.x] += red[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (sub == 0 && p0 < npair)
-      partial[static_cast<int64_t>(blockIdx.x) * npair + p0] = red[threadIdx.x];
-  } else {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int pidx = threadIdx.x + q * kThreads;
-      if (pidx < npair) partial[static_cast<int64_t>(blockIdx.x) * npair + pidx] = acc[q];
+  for (int a = 0; a < kGB; ++a)
+#pragma unroll
+    for (int b = 0; b < kGB; ++b) {
+      double x = acc[a][b];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o);
+      if (lane == 0) red[wv][a * kGB + b] = x;
+    }
+  __syncthreads();
+  if (threadIdx.x < kGB * kGB) {
+    const int a = threadIdx.x / kGB, b = threadIdx.x % kGB;
+    if (a < nu && b < nv) {
+      double x = 0.0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) x += red[w][threadIdx.x];
+      partial[static_cast<int64_t>(blockIdx.x) * tu * tv + (i0 + a) * tv + (j0 + b)] = x;
     }
   }
 }
@@ -288,9 +278,11 @@ struct BlockWs {
   int nwg = 0;
 };
 
-int gram_grid(int64_t nu) {
-  int64_t g = (nu + kTileRows - 1) / kTileRows;
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 512)));
+// Rows per workgroup of the streamed Gram kernel: enough rows per thread that the final
+// reduction is a small share of the work.
+int gram_rb_grid(int64_t nu) {
+  int64_t g = (nu + 16 * kThreads - 1) / (16 * kThreads);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 256)));
 }
 
 int rows_grid(int64_t nu) {
@@ -319,7 +311,7 @@ mm_status ensure_ws(Plan* P, BlockWs& ws, int t) {
   MM_TRY(alloc(reinterpret_cast<void**>(&ws.W), vec));
   MM_TRY(alloc(reinterpret_cast<void**>(&ws.MR), vec));
   MM_TRY(alloc(reinterpret_cast<void**>(&ws.small), sizeof(double) * 4 * kMaxT * kMaxT));
-  ws.nwg = std::max(gram_grid(nu), rows_grid(nu));
+  ws.nwg = std::max(gram_rb_grid(nu), rows_grid(nu));
   MM_TRY(alloc(reinterpret_cast<void**>(&ws.partial),
                sizeof(double) * static_cast<size_t>(ws.nwg) * kMaxT * kMaxT));
   MM_TRY(alloc(reinterpret_cast<void**>(&ws.cols), sizeof(int32_t) * kMaxT));
@@ -336,10 +328,17 @@ void free_ws(BlockWs& ws) {
 }
 
 // Gram U^T V (tu x tv, row-major) to the host.
+void launch_gram(const double* U, int tu, const double* V, int tv, int64_t nu, double* partial,
+                 int g, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(g),
+                  static_cast<unsigned>(((tu + kGB - 1) / kGB) * ((tv + kGB - 1) / kGB)));
+  hipLaunchKernelGGL(k_gram_rb, grid, dim3(kThreads), 0, s, U, tu, nu, V, tv, nu, nu, partial);
+}
+
 mm_status gram(const double* U, int tu, const double* V, int tv, int64_t nu, BlockWs& ws,
                std::vector<double>& out, hipStream_t s) {
-  const int g = gram_grid(nu);
-  hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V, tv, nu, nu, ws.partial);
+  const int g = gram_rb_grid(nu);
+  launch_gram(U, tu, V, tv, nu, ws.partial, g, s);
   const int count = tu * tv;
   hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(count)), dim3(kThreads), 0, s, ws.partial, g,
                      count, ws.small);
@@ -355,12 +354,12 @@ mm_status gram(const double* U, int tu, const double* V, int tv, int64_t nu, Blo
 mm_status gram_pair(const double* U, int tu, const double* V1, int tv1, const double* V2, int tv2,
                     int64_t nu, BlockWs& ws, std::vector<double>& out1, std::vector<double>& out2,
                     hipStream_t s) {
-  const int g = gram_grid(nu);
+  const int g = gram_rb_grid(nu);
   const int c1 = tu * tv1, c2 = tu * tv2;
-  hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V1, tv1, nu, nu, ws.partial);
+  launch_gram(U, tu, V1, tv1, nu, ws.partial, g, s);
   hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c1)), dim3(kThreads), 0, s, ws.partial, g, c1,
                      ws.small);
-  hipLaunchKernelGGL(k_gram, dim3(g), dim3(kThreads), 0, s, U, tu, nu, V2, tv2, nu, nu, ws.partial);
+  launch_gram(U, tu, V2, tv2, nu, ws.partial, g, s);
   hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c2)), dim3(kThreads), 0, s, ws.partial, g, c2,
                      ws.small + c1);
   MM_HIP_TRY(hipGetLastError());
