@@ -8,8 +8,10 @@
 // the segment tables and sizes the allocations.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
 #include <type_traits>
+#include <unordered_map>
 
 #include "mm_internal.h"
 #include "wave_runs.h"
@@ -570,15 +572,110 @@ std::shared_mutex& alloc_gate() {
   return m;
 }
 
+// Device memory of plans, workspaces and temporaries goes through a caching allocator.  A freed
+// block is kept (per device, keyed by its size) and handed to a later allocation that it fits
+// within an eighth, so that the repeated plan builds and solves of a serving loop do not map and
+// unmap gigabytes each time.  A free first synchronises the block's device, as hipFree does, so a
+// block is never handed out while earlier work may still touch it (the allocation gate keeps
+// that synchronisation away from graph captures).  Each device's cache holds at most a quarter
+// of its memory, the largest blocks released first beyond that, and is emptied when hipMalloc
+// fails.
+namespace {
+
+struct DevCache {
+  std::multimap<size_t, void*> blocks;  // cached blocks by size
+  size_t bytes = 0;
+  size_t cap = 0;
+};
+
+struct Allocation {
+  int device;
+  size_t bytes;
+};
+
+std::unordered_map<void*, Allocation>& allocations() {
+  static std::unordered_map<void*, Allocation> m;
+  return m;
+}
+
+std::map<int, DevCache>& dev_caches() {
+  static std::map<int, DevCache> m;
+  return m;
+}
+
+size_t rounded(size_t b) {
+  const size_t g = b <= (size_t{1} << 20) ? 256 : (size_t{1} << 16);
+  return (b + g - 1) / g * g;
+}
+
+// Release cached blocks of `c` (current device) until at most `keep` bytes stay cached.
+void release_cached(DevCache& c, size_t keep) {
+  while (c.bytes > keep && !c.blocks.empty()) {
+    auto it = std::prev(c.blocks.end());
+    c.bytes -= it->first;
+    allocations().erase(it->second);
+    (void)hipFree(it->second);
+    c.blocks.erase(it);
+  }
+}
+
+}  // namespace
+
 hipError_t dev_malloc(void** p, size_t bytes) {
   std::unique_lock<std::shared_mutex> lock(alloc_gate());
-  return hipMalloc(p, bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  DevCache& c = dev_caches()[dev];
+  if (c.cap == 0) {
+    size_t free_b = 0, total_b = 0;
+    c.cap = hipMemGetInfo(&free_b, &total_b) == hipSuccess ? total_b / 4 : (size_t{1} << 30);
+  }
+  const size_t want = rounded(bytes == 0 ? 1 : bytes);
+  auto it = c.blocks.lower_bound(want);
+  if (it != c.blocks.end() && it->first <= want + want / 8) {
+    *p = it->second;
+    c.bytes -= it->first;
+    c.blocks.erase(it);
+    return hipSuccess;
+  }
+  e = hipMalloc(p, want);
+  if (e != hipSuccess && !c.blocks.empty()) {
+    (void)hipGetLastError();  // the failure is recovered from: do not leave it for later checks
+    release_cached(c, 0);
+    e = hipMalloc(p, want);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  allocations()[*p] = Allocation{dev, want};
+  return hipSuccess;
 }
 
 void dev_free(void* p) {
   if (p == nullptr) return;
   std::unique_lock<std::shared_mutex> lock(alloc_gate());
-  (void)hipFree(p);
+  auto it = allocations().find(p);
+  if (it == allocations().end()) {
+    (void)hipFree(p);
+    return;
+  }
+  const Allocation a = it->second;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = a.device;
+  if (cur != a.device) (void)hipSetDevice(a.device);
+  (void)hipDeviceSynchronize();
+  DevCache& c = dev_caches()[a.device];
+  if (a.bytes > c.cap) {
+    allocations().erase(it);
+    (void)hipFree(p);
+  } else {
+    c.blocks.emplace(a.bytes, p);
+    c.bytes += a.bytes;
+    release_cached(c, c.cap);
+  }
+  if (cur != a.device) (void)hipSetDevice(cur);
 }
 
 bool needs_time_buffers(const Plan* P) {
