@@ -1,14 +1,17 @@
 // Preconditioned conjugate gradient (Alg. 1) on the device.
 //
 // Per iteration: q = A p (un-pointing, Toeplitz product, pointing), then three pixel-domain
-// kernels and two one-workgroup scalar kernels:
-//   k_dot_pq     partial sums of <p, q>
-//   k_alpha      alpha = <r, z> / <p, q> (breakdown flag when <p, q> <= 0)
-//   k_update     x += alpha p, r -= alpha q, z = M_BD r, q = 0; partials of ||r||^2, <r, z>
-//   k_beta       stop test ||r|| < eps ||b||, beta = <r', z'> / <r, z>, iteration count
+// kernels:
+//   k_dot_pq     partial sums of <p, q>; the workgroup that arrives last sums the partials and
+//                sets alpha = <r, z> / <p, q> (breakdown flag when <p, q> <= 0)
+//   k_update     x += alpha p, r -= alpha q, z = M_BD r, q = 0; partials of ||r||^2, <r, z>;
+//                the last workgroup takes the stop test ||r|| < eps ||b||, beta = <r', z'> /
+//                <r, z> and the iteration count (k_beta, a one-workgroup kernel, does that
+//                instead when the two-level preconditioner replaces z after the update)
 //   k_direction  p = z + beta p
 // All scalars live in a device CgState and all reductions are FP64 with a fixed summation
-// order (deterministic).  Every kernel returns at once when the state's `done` flag is set,
+// order (deterministic): the last-arriving workgroup sums the partials of all workgroups in
+// index order, whichever workgroup that is.  Every kernel returns at once when the state's `done` flag is set,
 // so iterations can be queued (or replayed from a captured graph) in chunks and the host only
 // reads the state between chunks.  Zeroing is done by kernels (no memset nodes in graphs).
 #include <chrono>
@@ -40,6 +43,23 @@ __device__ __forceinline__ double reduce_partials(const double* p, int n, double
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += kThreads) v += p[i];
   return block_sum(v, sh);
+}
+
+// Arrival of a workgroup after its partials are written (thread 0 wrote them): true in every
+// thread of the last workgroup to arrive, which then sees the partials of all workgroups and
+// re-arms the counter for the next kernel.  Release (fence, then count) and acquire (count,
+// then fence) at device scope.
+__device__ __forceinline__ bool last_to_arrive(int32_t* arrive) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(arrive, 1) == static_cast<int>(gridDim.x) - 1;
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  if (threadIdx.x == 0) *arrive = 0;
+  return true;
 }
 
 // z = M_BD r for pixel i of a [*, n_kept, 3] layout (minv shared across columns).
@@ -119,6 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_init_state(CgState* st, const doub
     st->pq = 0.0;
     st->iter = 0;
     st->max_iter = max_iter;
+    st->arrive = 0;
     if (bb == 0.0 || rr < st->tol2bb) {
       st->done = 1;
     } else if (!(rz > 0.0)) {
@@ -129,9 +150,10 @@ __global__ __launch_bounds__(kThreads) void k_init_state(CgState* st, const doub
   }
 }
 
+// <p, q> partials; the last workgroup sets alpha (nrb == gridDim.x).
 __global__ __launch_bounds__(kThreads) void k_dot_pq(const double* __restrict__ p,
                                                      const double* __restrict__ q, int64_t n,
-                                                     double* partial, const CgState* st) {
+                                                     double* partial, CgState* st, int nrb) {
   __shared__ double sh[kThreads / 64];
   if (st->done) return;
   double v = 0.0;
@@ -140,11 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_dot_pq(const double* __restrict__ 
     v += p[i] * q[i];
   const double s = block_sum(v, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(kThreads) void k_alpha(CgState* st, const double* partial, int nrb) {
-  __shared__ double sh[kThreads / 64];
-  if (st->done) return;
+  if (!last_to_arrive(&st->arrive)) return;
   const double pq = reduce_partials(partial, nrb, sh);
   if (threadIdx.x == 0) {
     st->pq = pq;
@@ -156,11 +174,33 @@ __global__ __launch_bounds__(kThreads) void k_alpha(CgState* st, const double* p
   }
 }
 
+// The stop test and beta from the ||r||^2 and <r, z> partials (one workgroup).
+__device__ __forceinline__ void finish_iteration(CgState* st, const double* partial, int nrb,
+                                                 double* sh) {
+  const double rr = reduce_partials(partial, nrb, sh);
+  const double rz = reduce_partials(partial + nrb, nrb, sh);
+  if (threadIdx.x == 0) {
+    st->iter += 1;
+    st->rr = rr;
+    if (rr < st->tol2bb) {
+      st->done = 1;
+    } else if (st->iter >= st->max_iter) {
+      st->done = 3;
+    } else if (!(rz > 0.0)) {
+      st->done = 2;
+    } else {
+      st->beta = rz / st->rz;
+      st->rz = rz;
+    }
+  }
+}
+
+template <bool kFinish>
 __global__ __launch_bounds__(kThreads) void k_update(const double* __restrict__ minv, double* x,
                                                      double* r, double* z,
                                                      const double* __restrict__ p, double* q,
                                                      int64_t n_kept, double* partial, int nrb,
-                                                     const CgState* st) {
+                                                     CgState* st) {
   __shared__ double sh[kThreads / 64];
   if (st->done) return;
   const double alpha = st->alpha;
@@ -188,27 +228,15 @@ __global__ __launch_bounds__(kThreads) void k_update(const double* __restrict__ 
     partial[blockIdx.x] = s0;
     partial[nrb + blockIdx.x] = s1;
   }
+  if constexpr (kFinish) {
+    if (last_to_arrive(&st->arrive)) finish_iteration(st, partial, nrb, sh);
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_beta(CgState* st, const double* partial, int nrb) {
   __shared__ double sh[kThreads / 64];
   if (st->done) return;
-  const double rr = reduce_partials(partial, nrb, sh);
-  const double rz = reduce_partials(partial + nrb, nrb, sh);
-  if (threadIdx.x == 0) {
-    st->iter += 1;
-    st->rr = rr;
-    if (rr < st->tol2bb) {
-      st->done = 1;
-    } else if (st->iter >= st->max_iter) {
-      st->done = 3;
-    } else if (!(rz > 0.0)) {
-      st->done = 2;
-    } else {
-      st->beta = rz / st->rz;
-      st->rz = rz;
-    }
-  }
+  finish_iteration(st, partial, nrb, sh);
 }
 
 __global__ __launch_bounds__(kThreads) void k_direction(const double* __restrict__ z, double* p,
@@ -288,12 +316,16 @@ mm_status iteration(Plan* P, Work& W, double* x, bool two_level, hipStream_t s) 
   }
   TimedLaunch tl(P, K_CG, s);
   hipLaunchKernelGGL(k_dot_pq, dim3(nrb), dim3(kThreads), 0, s, W.p, W.q, 3 * nk, W.partial,
-                     W.state);
-  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
-  hipLaunchKernelGGL(k_update, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z, W.p,
-                     W.q, nk, W.partial, nrb, W.state);
-  if (two_level) MM_TRY(deflation_apply(P, W.r, W.z, nullptr, W.partial, nrb, done, s));
-  hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
+                     W.state, nrb);
+  if (two_level) {
+    hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z,
+                       W.p, W.q, nk, W.partial, nrb, W.state);
+    MM_TRY(deflation_apply(P, W.r, W.z, nullptr, W.partial, nrb, done, s));
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
+  } else {
+    hipLaunchKernelGGL(k_update<true>, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z,
+                       W.p, W.q, nk, W.partial, nrb, W.state);
+  }
   hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, W.z, W.p, 3 * nk, W.state);
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
