@@ -348,8 +348,11 @@ def run_serving(args, mm, torch, dev):
     log(f"[bench] serving pool of {len(pool)} geometries, {n_req} requests, "
         f"generated in {time.time() - t0:.1f} s")
     used = sorted(set(int(g) for g in geom))
+    # segment lengths tuned per geometry shape (the first plan of a shape times the candidates,
+    # in the sizing pass below; later plans of the shape reuse the choice)
+    fft = args.fft_size
     geoms = [mm.make_geometry(di["pix"], di["wq"], di["wu"], p.n_pix_global, p.blk_start,
-                              p.blk_len, p.blk_band, p.bands, p.det_offset)
+                              p.blk_len, p.blk_band, p.bands, p.det_offset, fft_size=fft)
              for p, di in zip(pool, dev_in)]
     torch.cuda.synchronize()
     stream = torch.cuda.Stream(device=dev)
@@ -362,7 +365,7 @@ def run_serving(args, mm, torch, dev):
         with torch.cuda.stream(stream):
             pl = mm.Plan(dev_in[gi]["pix"], dev_in[gi]["wq"], dev_in[gi]["wu"], p.n_pix_global,
                          p.blk_start, p.blk_len, p.blk_band, p.bands, det_offset=p.det_offset,
-                         stream=stream)
+                         fft_size=fft, stream=stream)
         n_kept[gi] = pl.n_kept
         pl.close()
     x_seq = [torch.empty((int(ks[i]), n_kept[geom[i]], 3), dtype=torch.float64, device=dev)
@@ -387,7 +390,7 @@ def run_serving(args, mm, torch, dev):
                     p, di = pool[gi], dev_in[gi]
                     plans[gi] = mm.Plan(di["pix"], di["wq"], di["wu"], p.n_pix_global,
                                         p.blk_start, p.blk_len, p.blk_band, p.bands,
-                                        det_offset=p.det_offset, stream=stream)
+                                        det_offset=p.det_offset, fft_size=fft, stream=stream)
                 k = int(ks[i])
                 _, info = plans[gi].pcg_solve(dev_in[gi]["d"][:k], x=x_seq[i], tol=args.tol,
                                               stream=stream)
@@ -452,7 +455,8 @@ def run_serving(args, mm, torch, dev):
         with torch.cuda.stream(stream):
             p, di = pool[gi], dev_in[gi]
             pl = mm.Plan(di["pix"], di["wq"], di["wu"], p.n_pix_global, p.blk_start, p.blk_len,
-                         p.blk_band, p.bands, det_offset=p.det_offset, stream=stream)
+                         p.blk_band, p.bands, det_offset=p.det_offset, fft_size=fft,
+                         stream=stream)
             pl.pcg_solve(di["d"][:1], tol=args.tol, stream=stream)
             pl.close()
     torch.cuda.synchronize()
@@ -522,7 +526,7 @@ def run_serving(args, mm, torch, dev):
                    "requests": n_req, "geometries_used": len(used), "rhs": n_rhs,
                    "tod_samples_x_rhs": work, "slots": args.slots, "load": args.load,
                    "arrival_rate_per_s": round(rate, 3), "tol": args.tol,
-                   "parallelism": "single GPU"},
+                   "fft_size": fft, "parallelism": "single GPU"},
         "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99),
                    "saturated_requests_per_s": round(n_req / t_srv, 3),
                    "saturated_rhs_solves_per_s": round(n_rhs / t_srv, 3),
@@ -715,6 +719,9 @@ def main():
     ap.add_argument("--defl-m", type=int, default=64,
                     help="batched workload: Lanczos steps of the two-level preconditioner "
                          "(0: skip that comparison)")
+    ap.add_argument("--fft-size", type=int, default=-1,
+                    help="serving workloads: segment length of the plans (-1: tuned per shape, "
+                         "0: the rule's length)")
     ap.add_argument("--large-work", type=int, default=1 << 26,
                     help="serving workloads: requests of samples x RHS from this size are large "
                          "(0: one class)")

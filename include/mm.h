@@ -76,7 +76,12 @@ typedef struct mm_server mm_server_t;
  *   cond_max    excision threshold on the 2-norm condition number of each pixel's 3x3 BJ
  *               block; <= 0 selects 1e3.  Pixels with fewer than 3 hits are excised too.
  *   toeplitz_algo  MM_TOEPLITZ_*; fft_size  real FFT length for the overlap-save product
- *               (power of two in [2^11, 2^17], > 2 lambda_max), 0 = automatic.  Lengths up
+ *               (power of two in [2^11, 2^17], > 2 lambda_max), 0 = automatic (the smallest
+ *               power of two >= 4 lambda_max, with the exceptions of the kernels' limits),
+ *               -1 = tuned: the plan is built at that length N0 and at 2 N0 and 4 N0 (up to
+ *               2^17), one system product is timed on each and the fastest is kept; the choice
+ *               is remembered for plans of the same shape (samples, blocks, lambda_max, flags,
+ *               precision, device) for the life of the process.  Lengths up
  *               to 2^15 run in one CU's LDS (fused with the pointing products); 2^16 and 2^17
  *               (lambda up to 2^15 and beyond) use a four-step transform through one device
  *               tile per CU, fused with the pointing products as well.

@@ -9,7 +9,9 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 #include <type_traits>
 #include <unordered_map>
 
@@ -776,7 +778,133 @@ void destroy_plan(Plan* P) {
   delete P;
 }
 
+namespace {
+
+// FFT-length tuning (fft_size = -1): the shapes already tuned in this process, keyed by what
+// decides the segment table and its kernels.
+struct FftTuneKey {
+  int64_t n_samples;
+  int32_t n_blocks, lambda_max, flags, precision, device;
+  bool operator<(const FftTuneKey& o) const {
+    return std::tie(n_samples, n_blocks, lambda_max, flags, precision, device) <
+           std::tie(o.n_samples, o.n_blocks, o.lambda_max, o.flags, o.precision, o.device);
+  }
+};
+
+std::mutex& fft_tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+std::map<FftTuneKey, int32_t>& fft_tuned() {
+  static std::map<FftTuneKey, int32_t> m;
+  return m;
+}
+
+// Milliseconds of one system product of a built plan (mean of three after one warm-up).
+mm_status time_product(Plan* P, hipStream_t s, double* ms) {
+  const int64_t nu = 3 * P->n_kept;
+  double* x = nullptr;
+  double* y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Cleanup {
+    double*& x;
+    double*& y;
+    hipEvent_t& e0;
+    hipEvent_t& e1;
+    ~Cleanup() {
+      dev_free(x);
+      dev_free(y);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } cleanup{x, y, e0, e1};
+  if (dev_malloc(reinterpret_cast<void**>(&x), sizeof(double) * std::max<int64_t>(nu, 1)) !=
+          hipSuccess ||
+      dev_malloc(reinterpret_cast<void**>(&y), sizeof(double) * std::max<int64_t>(nu, 1)) !=
+          hipSuccess)
+    return fail(MM_ERR_OOM, "hipMalloc (FFT-length tuning)");
+  MM_TRY(launch_zero(x, nu, s));  // the product's work does not depend on the values
+  MM_HIP_TRY(hipEventCreate(&e0));
+  MM_HIP_TRY(hipEventCreate(&e1));
+  MM_TRY(apply_A(P, P->work, x, y, nullptr, s));
+  MM_HIP_TRY(hipEventRecord(e0, s));
+  for (int i = 0; i < 3; ++i) MM_TRY(apply_A(P, P->work, x, y, nullptr, s));
+  MM_HIP_TRY(hipEventRecord(e1, s));
+  MM_HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.0f;
+  MM_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / 3.0;
+  return MM_OK;
+}
+
+}  // namespace
+
+mm_status build_plan_fixed(const mm_geometry* g, hipStream_t s, Plan** out);
+
+// fft_size = -1: the plan is built at the rule's length N0 and at 2 N0 and 4 N0 (up to 2^17),
+// one system product is timed on each, and the fastest is kept.  The choice is remembered for
+// the shape, so later plans of the same shape are built once.
 mm_status build_plan(const mm_geometry* g, hipStream_t s, Plan** out) {
+  *out = nullptr;
+  if (g->fft_size < -1) return fail(MM_ERR_INVALID, "fft_size must be -1 (tuned), 0 or a length");
+  if (g->fft_size != -1) return build_plan_fixed(g, s, out);
+  int32_t lambda_max = 0;
+  for (int32_t b = 0; b < g->n_bands; ++b)
+    if (g->band_ncoef) lambda_max = std::max(lambda_max, g->band_ncoef[b] - 1);
+  mm_geometry h = *g;
+  h.fft_size = 0;
+  const bool fft = g->toeplitz_algo == MM_TOEPLITZ_FFT ||
+                   (g->toeplitz_algo == MM_TOEPLITZ_AUTO && lambda_max > 32);
+  if (!fft || lambda_max <= 0 || g->n_poly > 0) return build_plan_fixed(&h, s, out);
+  int dev = 0;
+  MM_HIP_TRY(hipGetDevice(&dev));
+  const FftTuneKey key{g->n_samples, g->n_blocks, lambda_max, g->flags, g->precision, dev};
+  {
+    std::lock_guard<std::mutex> lk(fft_tune_mutex());
+    auto it = fft_tuned().find(key);
+    if (it != fft_tuned().end()) {
+      h.fft_size = it->second;
+      return build_plan_fixed(&h, s, out);
+    }
+  }
+  const int32_t n0 = choose_fft_size(lambda_max);
+  if (n0 == 0) return build_plan_fixed(&h, s, out);  // reports the unsupported length
+  Plan* best = nullptr;
+  double best_ms = 0.0;
+  for (int32_t n = n0; n <= (1 << 17); n *= 2) {
+    if (!fft_size_supported(n)) continue;
+    h.fft_size = n;
+    Plan* cand = nullptr;
+    const mm_status st = build_plan_fixed(&h, s, &cand);
+    if (st != MM_OK) {
+      if (best == nullptr && n == n0) return st;  // the rule's own length must build
+      continue;
+    }
+    double ms = 0.0;
+    const mm_status tt = time_product(cand, s, &ms);
+    if (tt != MM_OK) {
+      destroy_plan(cand);
+      if (best) destroy_plan(best);
+      return tt;
+    }
+    if (best == nullptr || ms < best_ms) {
+      if (best) destroy_plan(best);
+      best = cand;
+      best_ms = ms;
+    } else {
+      destroy_plan(cand);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(fft_tune_mutex());
+    fft_tuned()[key] = best->fft_n;
+  }
+  *out = best;
+  return MM_OK;
+}
+
+mm_status build_plan_fixed(const mm_geometry* g, hipStream_t s, Plan** out) {
   *out = nullptr;
   std::vector<int> order;
   int32_t lambda_max = 0;

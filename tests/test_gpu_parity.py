@@ -213,6 +213,25 @@ def test_apply_A_every_fft_size(gpu_lib, fft_size, flags):
     assert np.all(np.abs(b - bw) <= _A_bound(plan, ref, dm))
 
 
+def test_fft_length_tuning(gpu_lib):
+    # lambda 901: the rule's length is 4096; the tuner times 4096, 8192 and 16384 and keeps one,
+    # and a second plan of the same shape takes the remembered length without tuning
+    prob = synth.make_ground(cfg_id=28, n_dets=2, samples_per_det=50001, interval=20011,
+                             side=16, lam=901, flag_frac=0.01)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=-1)
+    n = plan.info["fft_size"]
+    assert n in (4096, 8192, 16384), plan.info
+    x = np.random.default_rng(12).standard_normal((ref.n_kept, 3))
+    y, want = plan.apply_A(_dev(x)).cpu().numpy(), O.apply_A(ref, x)
+    assert float(_rel(y, want)) <= 3e-6
+    assert np.all(np.abs(y - want) <= _A_bound(plan, ref, O.unpoint(ref, x)))
+    again = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=-1)
+    assert again.info["fft_size"] == n
+    with pytest.raises(gpu_lib.MMError):
+        _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=-2)
+
+
 @pytest.mark.parametrize("name", ["tiny", "random_flags_gaps", "ground_mini"])
 def test_precond_parity(gpu_lib, name):
     prob, ref = case(name)
