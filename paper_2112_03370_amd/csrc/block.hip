@@ -44,13 +44,24 @@ constexpr int kMaxT = 32;
 // took ~160 us per call for t = 8.)
 constexpr int kGB = 8;
 
+// Two products against the same U in one launch: pair blocks y < nb1 belong to U^T V1, the
+// rest to U^T V2 (tv2 = 0: one product); partial[x] holds the tu x tv1 entries, then the
+// tu x tv2 entries.
 __global__ __launch_bounds__(kThreads) void k_gram_rb(const double* __restrict__ U, int tu,
-                                                      int64_t ldu, const double* __restrict__ V,
-                                                      int tv, int64_t ldv, int64_t n,
+                                                      int64_t ldu, const double* __restrict__ V1,
+                                                      int tv1, const double* __restrict__ V2,
+                                                      int tv2, int64_t ldv, int64_t n,
                                                       double* __restrict__ partial) {
   __shared__ double red[kThreads / 64][kGB * kGB];
+  const int nbu = (tu + kGB - 1) / kGB;
+  const int nb1 = nbu * ((tv1 + kGB - 1) / kGB);
+  const bool second = static_cast<int>(blockIdx.y) >= nb1;
+  const double* __restrict__ V = second ? V2 : V1;
+  const int tv = second ? tv2 : tv1;
+  const int yb = second ? static_cast<int>(blockIdx.y) - nb1 : static_cast<int>(blockIdx.y);
+  const int64_t off = second ? static_cast<int64_t>(tu) * tv1 : 0;
   const int nbv = (tv + kGB - 1) / kGB;
-  const int i0 = (blockIdx.y / nbv) * kGB, j0 = (blockIdx.y % nbv) * kGB;
+  const int i0 = (yb / nbv) * kGB, j0 = (yb % nbv) * kGB;
   const int nu = min(kGB, tu - i0), nv = min(kGB, tv - j0);
   double acc[kGB][kGB];
 #pragma unroll
@@ -85,7 +96,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_rb(const double* __restrict__
       double x = 0.0;
 #pragma unroll
       for (int w = 0; w < kThreads / 64; ++w) x += red[w][threadIdx.x];
-      partial[static_cast<int64_t>(blockIdx.x) * tu * tv + (i0 + a) * tv + (j0 + b)] = x;
+      partial[static_cast<int64_t>(blockIdx.x) * tu * (tv1 + tv2) + off + (i0 + a) * tv +
+              (j0 + b)] = x;
     }
   }
 }
@@ -328,17 +340,18 @@ void free_ws(BlockWs& ws) {
 }
 
 // Gram U^T V (tu x tv, row-major) to the host.
-void launch_gram(const double* U, int tu, const double* V, int tv, int64_t nu, double* partial,
-                 int g, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(g),
-                  static_cast<unsigned>(((tu + kGB - 1) / kGB) * ((tv + kGB - 1) / kGB)));
-  hipLaunchKernelGGL(k_gram_rb, grid, dim3(kThreads), 0, s, U, tu, nu, V, tv, nu, nu, partial);
+void launch_gram(const double* U, int tu, const double* V1, int tv1, const double* V2, int tv2,
+                 int64_t nu, double* partial, int g, hipStream_t s) {
+  const int nbu = (tu + kGB - 1) / kGB;
+  const int nb = nbu * ((tv1 + kGB - 1) / kGB) + nbu * ((tv2 + kGB - 1) / kGB);
+  hipLaunchKernelGGL(k_gram_rb, dim3(static_cast<unsigned>(g), static_cast<unsigned>(nb)),
+                     dim3(kThreads), 0, s, U, tu, nu, V1, tv1, V2, tv2, nu, nu, partial);
 }
 
 mm_status gram(const double* U, int tu, const double* V, int tv, int64_t nu, BlockWs& ws,
                std::vector<double>& out, hipStream_t s) {
   const int g = gram_rb_grid(nu);
-  launch_gram(U, tu, V, tv, nu, ws.partial, g, s);
+  launch_gram(U, tu, V, tv, nullptr, 0, nu, ws.partial, g, s);
   const int count = tu * tv;
   hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(count)), dim3(kThreads), 0, s, ws.partial, g,
                      count, ws.small);
@@ -349,19 +362,15 @@ mm_status gram(const double* U, int tu, const double* V, int tv, int64_t nu, Blo
   return MM_OK;
 }
 
-// U^T V1 and U^T V2 to the host behind one synchronization (the second product's partials
-// overwrite the first's only after the first reduction, in stream order).
+// U^T V1 and U^T V2 to the host, one launch, one reduction and one synchronization.
 mm_status gram_pair(const double* U, int tu, const double* V1, int tv1, const double* V2, int tv2,
                     int64_t nu, BlockWs& ws, std::vector<double>& out1, std::vector<double>& out2,
                     hipStream_t s) {
   const int g = gram_rb_grid(nu);
   const int c1 = tu * tv1, c2 = tu * tv2;
-  launch_gram(U, tu, V1, tv1, nu, ws.partial, g, s);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c1)), dim3(kThreads), 0, s, ws.partial, g, c1,
-                     ws.small);
-  launch_gram(U, tu, V2, tv2, nu, ws.partial, g, s);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c2)), dim3(kThreads), 0, s, ws.partial, g, c2,
-                     ws.small + c1);
+  launch_gram(U, tu, V1, tv1, V2, tv2, nu, ws.partial, g, s);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(c1 + c2)), dim3(kThreads), 0, s, ws.partial,
+                     g, c1 + c2, ws.small);
   MM_HIP_TRY(hipGetLastError());
   std::vector<double> both(c1 + c2);
   MM_HIP_TRY(hipMemcpyAsync(both.data(), ws.small, sizeof(double) * (c1 + c2),
@@ -438,29 +447,42 @@ mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x
     const int g = rows_grid(nu);
     MM_TM_DISPATCH(k_block_update, tz, g, s, ws.Z, ws.W, tz, ws.R, ta, nu, x, ws.cols,
                    ws.small + kMaxT * kMaxT, ws.partial);
+    // ||R_j||^2, then MR = M R and H2 = W^T MR for every column still in the block, read back
+    // together behind one synchronization
+    constexpr int kRrOff = 2 * kMaxT * kMaxT, kH2Off = kRrOff + kMaxT;
     hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(ta)), dim3(kThreads), 0, s, ws.partial, g,
-                       ta, ws.small);
+                       ta, ws.small + kRrOff);
+    MM_TRY(launch_precond_multi(P, ws.R, ws.MR, ta, s));
+    const int gg = gram_rb_grid(nu);
+    launch_gram(ws.W, tz, ws.MR, ta, nullptr, 0, nu, ws.partial, gg, s);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(reduce_grid(tz * ta)), dim3(kThreads), 0, s,
+                       ws.partial, gg, tz * ta, ws.small + kH2Off);
     MM_HIP_TRY(hipGetLastError());
-    std::vector<double> rr(ta);
-    MM_HIP_TRY(hipMemcpyAsync(rr.data(), ws.small, sizeof(double) * ta, hipMemcpyDeviceToHost, s));
+    std::vector<double> back(kMaxT + static_cast<size_t>(tz) * ta);
+    MM_HIP_TRY(hipMemcpyAsync(back.data(), ws.small + kRrOff, sizeof(double) * back.size(),
+                              hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
     ++k;
-    // stop test per column; compact R to the remaining columns
+    // stop test per column; compact R and MR to the remaining columns
     std::vector<int32_t> nact;
-    std::vector<int> nslot;
+    std::vector<int> nslot, keep_idx;
     for (int i = 0; i < ta; ++i) {
       const int j = slot_of[i];
-      const double rel = std::sqrt(std::max(rr[i], 0.0)) / bnorm[j];
+      const double rel = std::sqrt(std::max(back[i], 0.0)) / bnorm[j];
       relres[j] = rel;
       iters[j] = k;
       if (rel < tol) {
         conv[j] = 1;
       } else {
-        if (static_cast<int>(nact.size()) != i)
+        if (static_cast<int>(nact.size()) != i) {
           MM_HIP_TRY(hipMemcpyAsync(ws.R + nact.size() * nu, ws.R + i * nu, sizeof(double) * nu,
                                     hipMemcpyDeviceToDevice, s));
+          MM_HIP_TRY(hipMemcpyAsync(ws.MR + nact.size() * nu, ws.MR + i * nu,
+                                    sizeof(double) * nu, hipMemcpyDeviceToDevice, s));
+        }
         nact.push_back(act[i]);
         nslot.push_back(j);
+        keep_idx.push_back(i);
       }
     }
     const int tn = static_cast<int>(nact.size());
@@ -468,8 +490,9 @@ mm_status solve_group(Plan* P, Work& Wk, const float* d, int64_t ld_d, double* x
       ta = 0;
       break;
     }
-    MM_TRY(launch_precond_multi(P, ws.R, ws.MR, tn, s));   // MR = M R
-    MM_TRY(gram(ws.W, tz, ws.MR, tn, nu, ws, H, s));       // H2 = W^T MR
+    H.assign(static_cast<size_t>(tz) * tn, 0.0);  // H2 = W^T MR on the remaining columns
+    for (int i = 0; i < tz; ++i)
+      for (int jj = 0; jj < tn; ++jj) H[i * tn + jj] = back[kMaxT + i * ta + keep_idx[jj]];
     matmul(Gi, H, tz, tn, A);                              // a2 = G^+ H2  (tz x tn)
     MM_HIP_TRY(hipMemcpyAsync(ws.small + kMaxT * kMaxT, A.data(), sizeof(double) * A.size(),
                               hipMemcpyHostToDevice, s));

@@ -403,7 +403,11 @@ mm_status apply_A_multi(Plan* P, Work& W, const double* x, int64_t ldx, double* 
   if (ncol <= 0 || P->n_kept == 0) return MM_OK;
   if (P->lambda_max != 0 && P->algo == MM_TOEPLITZ_FFT && P->fused &&
       P->precision == MM_PRECISION_MIXED) {
-    for (int32_t j = 0; j < ncol; ++j) MM_TRY(launch_zero(y + j * ldy, 3 * P->n_kept, s));
+    if (ldy == 3 * P->n_kept) {
+      MM_TRY(launch_zero(y, ncol * ldy, s));  // the columns are contiguous: one launch
+    } else {
+      for (int32_t j = 0; j < ncol; ++j) MM_TRY(launch_zero(y + j * ldy, 3 * P->n_kept, s));
+    }
     return launch_apply_fused(P, x, nullptr, y, nullptr, s, W.scratch, ncol, ldx, ldy);
   }
   for (int32_t j = 0; j < ncol; ++j) MM_TRY(apply_A(P, W, x + j * ldx, y + j * ldy, nullptr, s));
