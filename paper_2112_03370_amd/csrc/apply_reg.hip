@@ -38,6 +38,7 @@ constexpr int kRowB = 560;         // LDS stride of a k3 plane in the B <-> C tr
                                    // 39 % fewer bank conflicts than 544)
 constexpr int kLdsF = 32 * kRowB;  // floats of staging LDS
 constexpr int kLane = 8;           // consecutive samples per lane in the gather and scatter
+constexpr int kListed = 64;        // runs listed per wavefront and scatter round
 constexpr int kTab = 16 * kT + 8;  // symbol pairs per band in the kernel's read order
 constexpr int kW2 = 33;            // row stride of the W_512 table
 
@@ -455,7 +456,14 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __syncthreads();
 
   // ---- scatter the segment's outputs ----------------------------------------------------------
+  // Each wavefront reads its own 512 staged outputs per round; once read, that slice holds the
+  // wavefront's list of completed runs, flushed one FP64 value per lane.
   const AtomicFlush flush{y};
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  static_assert(kListed * (3 * sizeof(double) + sizeof(int)) <= 64 * kLane * sizeof(float),
+                "run list must fit the wavefront's slice of the staged outputs");
+  static_assert((kHalf + kT * kLane - 1) / (kT * kLane) * (kT * kLane) <= kLdsF,
+                "every round's slices lie inside the staging buffer");
   for (int base = 0; base < out_len; base += kT * kLane) {  // same trip count for every lane
     const int i0 = base + tid * kLane;
     const int64_t o = c.out0 + i0;
@@ -487,7 +495,9 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
       }
     }
-    wave_merge_runs_n<kLane, 3>(key, val, flush);
+    double* sval = reinterpret_cast<double*>(lds + base + 64 * kLane * wave);
+    int* skey = reinterpret_cast<int*>(sval + 3 * kListed);
+    wave_merge_runs_listed<kLane, 3, kListed, AtomicFlush, true>(key, val, flush, skey, sval);
   }
 }
 

@@ -217,6 +217,9 @@ struct XFlush {
     unsafeAtomicAdd(dst + 1, v[1]);
     unsafeAtomicAdd(dst + 2, v[2]);
   }
+  __device__ void one(int key, int c, double v) const {
+    unsafeAtomicAdd(y + 3 * static_cast<int64_t>(key) + c, v);
+  }
 };
 
 // ---- outputs of each segment, pointed back into the pixel domain -------------------------
@@ -648,6 +651,12 @@ __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
     if (o0 + 1 >= 0 && o0 + 1 < c.out_len) sh[xpad(o0 + 1)] = -v[s].y * inv_n;
   }
   __syncthreads();
+  // Each wavefront reads its own 512 staged outputs per round (out_len <= NC, so every round's
+  // slices lie inside sh); once read, that slice holds the wavefront's list of completed runs,
+  // flushed one FP64 value per lane.
+  constexpr int kXListed = 64;
+  static_assert(3 * kXListed + kXListed / 2 <= 512, "run list must fit a wavefront's slice");
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   for (int base = 0; base < c.out_len; base += 8 * T) {  // same trip count for every lane
     const int i0 = base + 8 * t;
     const int64_t o = c.out0 + i0;
@@ -701,7 +710,9 @@ __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
         }
       }
     }
-    wave_merge_runs_n<8, 3>(key, vv, XFlush{y});
+    double* sval = sh + xpad(base + 512 * wave);
+    int* skey = reinterpret_cast<int*>(sval + 3 * kXListed);
+    wave_merge_runs_listed<8, 3, kXListed, XFlush, true>(key, vv, XFlush{y}, skey, sval);
   }
 }
 

@@ -142,6 +142,9 @@ struct PointFlush {
     unsafeAtomicAdd(dst + 1, v[1]);
     unsafeAtomicAdd(dst + 2, v[2]);
   }
+  __device__ void one(int key, int c, double v) const {
+    unsafeAtomicAdd(y + 3 * static_cast<int64_t>(key) + c, v);
+  }
 };
 
 template <bool kVec>
@@ -198,7 +201,8 @@ __global__ __launch_bounds__(kThreads) void k_point(const int32_t* __restrict__ 
         }
       }
     }
-    wave_merge_runs_listed<kLane, 3, kListed>(key, v, flush, skey[wave], sval[wave]);
+    wave_merge_runs_listed<kLane, 3, kListed, PointFlush, true>(key, v, flush, skey[wave],
+                                                               sval[wave]);
   }
 }
 

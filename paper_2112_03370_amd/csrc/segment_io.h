@@ -17,6 +17,9 @@ struct AtomicFlush {
     unsafeAtomicAdd(dst + 1, v[1]);
     unsafeAtomicAdd(dst + 2, v[2]);
   }
+  __device__ void one(int key, int c, double v) const {
+    unsafeAtomicAdd(y + 3 * static_cast<int64_t>(key) + c, v);
+  }
 };
 
 template <bool kFromData>

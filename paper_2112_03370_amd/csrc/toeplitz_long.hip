@@ -246,11 +246,19 @@ __device__ __forceinline__ void fill_lane(const LongArgs& a, const double* __res
   }
 }
 
+// Runs listed per wavefront and drain round before their atomics; the list lives in the
+// wavefront's own row pieces of the group buffer, which it has read by then.
+constexpr int kListed = 64;
+static_assert(kListed * (3 * sizeof(double) + sizeof(int)) <= kWaveRows * kS * sizeof(float2),
+              "run list must fit the wavefront's row pieces");
+
 // Output samples [o, o + kLane) of a segment (only those in [0, out_len) exist).  The fused
-// form must be reached by whole wavefronts (the run merge exchanges lanes).
+// form must be reached by whole wavefronts (the run merge exchanges lanes); `list` is the
+// wavefront's LDS for its run list (no other wavefront touches it during the call).
 template <int IO>
 __device__ __forceinline__ void drain_lane(const LongArgs& a, double* __restrict__ y,
-                                           const Chunk& c, int o, const float (&v)[kLane]) {
+                                           const Chunk& c, int o, const float (&v)[kLane],
+                                           float2* list) {
   const int64_t go = c.out0 + o;
   const bool inside = o >= 0 && o + kLane <= c.out_len && (go & 3) == 0;
   if constexpr (IO == kIoPlain) {
@@ -291,7 +299,10 @@ __device__ __forceinline__ void drain_lane(const LongArgs& a, double* __restrict
         }
       }
     }
-    wave_merge_runs_n<kLane, 3>(key, val, AtomicFlush{y});
+    double* sval = reinterpret_cast<double*>(list);
+    int* skey = reinterpret_cast<int*>(sval + 3 * kListed);
+    wave_merge_runs_listed<kLane, 3, kListed, AtomicFlush, true>(key, val, AtomicFlush{y}, skey,
+                                                                 sval);
   }
 }
 
@@ -330,8 +341,8 @@ __global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int round = 0;; ++round) {
     const int item = work_item(blockIdx.x, gridDim.x, round);
     if (item >= a.n_work) break;
-    // lane roles: transform slot (lane) and butterfly / row (wavefront); 16 lanes of 8
-    // samples per 128-sample row piece in the fills and drains
+    // lane roles: transform slot (lane) and butterfly / row (wavefront); kRowLanes lanes of
+    // 8 samples per 2 kG-sample row piece in the fills and drains
     const int lt = opaque(tid);
     const int tc = lt % kG, tw_ = lt / kG;                        // transform, butterfly
     const int fr = lt / kRowLanes, fq = lt % kRowLanes;           // row piece, lane in it
@@ -434,7 +445,7 @@ __global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(4))) void k
           v[2 * j + 1] = -F.y;
         }
         const int o = 2 * (m1 * kN2 + kG * g) + kLane * fq - a.lam;
-        drain_lane<IO>(a, y, c, o, v);
+        drain_lane<IO>(a, y, c, o, v, buf + m1w * kS);
       }
       __syncthreads();
     }

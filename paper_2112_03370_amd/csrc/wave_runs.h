@@ -126,7 +126,13 @@ __device__ __forceinline__ int wave_exclusive_count(int c, int lane, int& total)
 // lane position where some lane closes a run inside it, which on scans with short runs (a
 // circle clipping pixel corners) means several rounds of nearly idle atomic instructions per
 // wavefront.  Runs beyond CAP are flushed directly.
-template <int SPL, int NV, int CAP, class Flush>
+//
+// kByComponent flushes the list one value per lane instead (lanes NV r .. NV r + NV - 1 take the
+// NV values of run r, through flush.one(key, component, value)): ceil(NV R / 64) instructions,
+// and the values of one run go out in one instruction.  Where the runs of a wavefront fall on
+// different cache lines (pixel ids far apart along the scan), a run then costs one memory-side
+// atomic request instead of NV.
+template <int SPL, int NV, int CAP, class Flush, bool kByComponent = false>
 __device__ __forceinline__ void wave_merge_runs_listed(const int (&key)[SPL],
                                                        const double (&v)[SPL][NV],
                                                        const Flush& flush, int* skey,
@@ -247,15 +253,25 @@ __device__ __forceinline__ void wave_merge_runs_listed(const int (&key)[SPL],
     }
   }
 
-  // ---- one listed run per lane ---------------------------------------------------------------
+  // ---- one listed run (or one value of one) per lane ---------------------------------------
   wave_lds_sync();  // runs listed by other lanes of the wavefront are visible
   const int listed = r_in + r_ht < CAP ? r_in + r_ht : CAP;
-  for (int r = lane; r - lane < listed; r += 64) {
-    if (r < listed) {
-      double w[NV];
+  if constexpr (kByComponent) {
+    const int n = listed * NV;
+    for (int e = lane; e - lane < n; e += 64) {
+      if (e < n) {
+        const int r = e / NV;
+        flush.one(skey[r], e - r * NV, sval[e]);
+      }
+    }
+  } else {
+    for (int r = lane; r - lane < listed; r += 64) {
+      if (r < listed) {
+        double w[NV];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) w[c] = sval[r * NV + c];
-      flush(skey[r], w);
+        for (int c = 0; c < NV; ++c) w[c] = sval[r * NV + c];
+        flush(skey[r], w);
+      }
     }
   }
 }

@@ -446,6 +446,23 @@ def test_apply_A_long_segments(gpu_lib, fft_size, lam, flags):
     assert np.all(np.abs(b - bw) <= _A_bound(plan, ref, dm))
 
 
+@pytest.mark.parametrize("dwell", [1, 3])
+def test_apply_A_long_segments_short_runs(gpu_lib, dwell):
+    # The long-segment scatter lists up to 64 runs per wavefront and drain round and flushes them
+    # one value per lane; one or three samples per pixel (170 to 512 runs per 512 samples)
+    # overflow the list, and the runs beyond it are flushed directly.
+    prob = synth.make_ground(cfg_id=28, n_dets=2, samples_per_det=200003, interval=100003,
+                             side=40, dwell=dwell, lam=12001, flag_frac=0.01)
+    ref = O.plan_from_problem(prob)
+    plan = _plan(gpu_lib, prob, toeplitz_algo=gpu_lib.TOEPLITZ_FFT, fft_size=65536)
+    assert plan.info["fused"] == 3, plan.info
+    x = np.random.default_rng(12).standard_normal((ref.n_kept, 3))
+    y, want = plan.apply_A(_dev(x)).cpu().numpy(), O.apply_A(ref, x)
+    err = float(_rel(y, want))
+    assert err <= 3e-6, err
+    assert np.all(np.abs(y - want) <= _A_bound(plan, ref, O.unpoint(ref, x)))
+
+
 def test_satellite_long_band_pcg(gpu_lib):
     prob = synth.make_satellite(cfg_id=26, n_dets=2, samples_per_det=1 << 18, interval=1 << 17,
                                 n_rings=32, n_phi=64, lam=1 << 14, fknee=0.05, fsample=20.0)
