@@ -179,6 +179,55 @@ __global__ __launch_bounds__(kXThreads) void k_x_pass(const double2* __restrict_
   for (int m = 0; m < R; ++m) out[o + m * p] = v[m];
 }
 
+// Radix-256 Stockham pass: the two radix-16 levels of a 256-point DFT in one read and one write
+// of the batch.  With j = 16 j1 + j2 and m = m1 + 16 m2,
+//   X[m1 + 16 m2] = sum_j2 W_16^(j2 m2) W_256^(j2 m1) sum_j1 W_16^(j1 m1) v[16 j1 + j2];
+// a workgroup takes 16 consecutive butterflies b (g = b mod 16 fastest, so each load and store
+// touches 16 consecutive points); thread (g, h) first runs the inner DFT over j1 for j2 = h, then,
+// after the exchange in LDS, the outer DFT over j2 for m1 = h.
+__global__ __launch_bounds__(kXThreads) void k_x_pass256(const double2* __restrict__ in,
+                                                         double2* __restrict__ out,
+                                                         const double2* __restrict__ tw, int NC,
+                                                         int p) {
+  static_assert(kXThreads == 256, "16 butterflies x 16 threads");
+  constexpr int R = 256;
+  __shared__ double2 sh[16 * 16 * 17];  // [m1][j2][g], rows of 16 padded to 17
+  const int L = NC / R;
+  const int g = static_cast<int>(threadIdx.x & 15u), h = static_cast<int>(threadIdx.x >> 4);
+  const int b = blockIdx.x * 16 + g;
+  const bool live = b < L;
+  const int64_t base = static_cast<int64_t>(blockIdx.y) * NC;
+  const int k = b & (p - 1);
+  double2 v[16];
+  if (live) {
+#pragma unroll
+    for (int j1 = 0; j1 < 16; ++j1) v[j1] = in[base + b + static_cast<int64_t>(16 * j1 + h) * L];
+    if (p > 1) {
+      // W_(pR)^(j k) = W_N^(2 j k NC / (p R)) with N = 2 NC, j = 16 j1 + h
+      const int step = 2 * k * (NC / (p * R));
+#pragma unroll
+      for (int j1 = 0; j1 < 16; ++j1)
+        if (16 * j1 + h > 0) v[j1] = cmul(v[j1], tw_n(tw, (16 * j1 + h) * step, NC));
+    }
+    dft<16>(v);
+    // W_256^(h m1) = W_N^(h m1 2 NC / 256)
+    const int s256 = 2 * NC / R;
+#pragma unroll
+    for (int m1 = 1; m1 < 16; ++m1) v[m1] = cmul(v[m1], tw_n(tw, h * m1 * s256, NC));
+#pragma unroll
+    for (int m1 = 0; m1 < 16; ++m1) sh[(m1 * 16 + h) * 17 + g] = v[m1];
+  }
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int j2 = 0; j2 < 16; ++j2) v[j2] = sh[(h * 16 + j2) * 17 + g];
+    dft<16>(v);
+    const int64_t o = base + static_cast<int64_t>(b - k) * R + k;
+#pragma unroll
+    for (int m2 = 0; m2 < 16; ++m2) out[o + static_cast<int64_t>(h + 16 * m2) * p] = v[m2];
+  }
+}
+
 // ---- real spectrum times the band symbol, repacked and conjugated -----------------------
 // From Z[k] and Z[NC - k] of the packed forward transform: even / odd half spectra
 // E = (Z[k] + conj Z[-k]) / 2, O = (Z[k] - conj Z[-k]) / (2i), X[k] = E + W_N^k O and
@@ -757,13 +806,21 @@ mm_status run_pass(const double2* in, double2* out, const double2* tw, int NC, i
   return MM_OK;
 }
 
-// Forward DFT of every segment of the batch: radix-16 passes, then the remaining factor.
+// Forward DFT of every segment of the batch: radix-256 passes (two radix-16 levels each
+// through LDS), then radix-16 passes, then the remaining factor.
 // Returns the tile holding the result (a or b).
 mm_status batch_fft(double2* a, double2* b, const double2* tw, int NC, int nseg, hipStream_t s,
                     double2** result) {
   double2* in = a;
   double2* out = b;
   int p = 1;
+  while (NC / p >= 256) {
+    hipLaunchKernelGGL(k_x_pass256, dim3((NC / 256 + 15) / 16, nseg), dim3(kXThreads), 0, s, in,
+                       out, tw, NC, p);
+    MM_HIP_TRY(hipGetLastError());
+    p *= 256;
+    std::swap(in, out);
+  }
   while (NC / p >= 16) {
     MM_TRY(run_pass<16>(in, out, tw, NC, p, nseg, s));
     p *= 16;

@@ -59,6 +59,10 @@ CASES = {
                                            interval=1 << 16, side=32, lam=8192), {}),
     "fft_2e17": (lambda: synth.make_ground(cfg_id=96, n_dets=2, samples_per_det=1 << 18,
                                            interval=3 << 16, side=32, lam=20000), {}),
+    # 2^16 points: one radix-256 pass, one radix-16 pass and one radix-8 pass per transform
+    "fft_2e16": (lambda: synth.make_ground(cfg_id=100, n_dets=2, samples_per_det=150001,
+                                           interval=70001, side=32, lam=12001, flag_frac=0.01),
+                 {"fft_size": 1 << 16}),
     # one workgroup per segment with the FP64 transform in registers (N = 2^12 .. 2^15, at most
     # N/2 outputs per segment): odd lambda, ragged intervals, flags
     "fused_2e12": (lambda: synth.make_ground(cfg_id=97, n_dets=3, samples_per_det=30011,
