@@ -2,18 +2,18 @@
 //
 // Per iteration: q = A p (un-pointing, Toeplitz product, pointing), then three pixel-domain
 // kernels:
-//   k_dot_pq     partial sums of <p, q>; the workgroup that arrives last sums the partials and
-//                sets alpha = <r, z> / <p, q> (breakdown flag when <p, q> <= 0)
-//   k_update     x += alpha p, r -= alpha q, z = M_BD r, q = 0; partials of ||r||^2, <r, z>;
-//                the last workgroup takes the stop test ||r|| < eps ||b||, beta = <r', z'> /
-//                <r, z> and the iteration count (k_beta, a one-workgroup kernel, does that
-//                instead when the two-level preconditioner replaces z after the update)
-//   k_direction  p = z + beta p
+//   k_dot_pq     partial sums of <p, q>
+//   k_update     alpha = <r, z> / <p, q> from those partials (breakdown flag when <p, q> <= 0),
+//                x += alpha p, r -= alpha q, z = M_BD r, q = 0; partials of ||r||^2, <r, z>
+//                (the two-level preconditioner then replaces z and its <r, z> partials)
+//   k_direction  the stop test ||r|| < eps ||b||, the iteration count and beta = <r', z'> /
+//                <r, z> from those partials, then p = z + beta p
 // All scalars live in a device CgState and all reductions are FP64 with a fixed summation
-// order (deterministic): the last-arriving workgroup sums the partials of all workgroups in
-// index order, whichever workgroup that is.  Every kernel returns at once when the state's `done` flag is set,
-// so iterations can be queued (or replayed from a captured graph) in chunks and the host only
-// reads the state between chunks.  Zeroing is done by kernels (no memset nodes in graphs).
+// order (deterministic): each workgroup that needs a scalar sums all partials of the previous
+// kernel in index order, so every workgroup holds the same value.  Every kernel returns at once
+// when the state's `done` flag is set, so iterations can be queued (or replayed from a captured
+// graph) in chunks and the host only reads the state between chunks.  Zeroing is done by
+// kernels (no memset nodes in graphs).
 #include <chrono>
 #include <cmath>
 
@@ -45,22 +45,11 @@ __device__ __forceinline__ double reduce_partials(const double* p, int n, double
   return block_sum(v, sh);
 }
 
-// Arrival of a workgroup after its partials are written (thread 0 wrote them): true in every
-// thread of the last workgroup to arrive, which then sees the partials of all workgroups and
-// re-arms the counter for the next kernel.  Release (fence, then count) and acquire (count,
-// then fence) at device scope.
-__device__ __forceinline__ bool last_to_arrive(int32_t* arrive) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(arrive, 1) == static_cast<int>(gridDim.x) - 1;
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  if (threadIdx.x == 0) *arrive = 0;
-  return true;
-}
+// Scalars of the recurrence: every workgroup of the kernel that needs alpha or beta sums the
+// previous kernel's per-workgroup partials itself, in the same fixed order, so all of them hold
+// the same value (the kernel boundary makes the partials visible; no fence or counter).
+// Workgroup 0 alone records the scalars in the state; the state fields that the other
+// workgroups read in that kernel were written one kernel earlier.
 
 // z = M_BD r for pixel i of a [*, n_kept, 3] layout (minv shared across columns).
 __device__ __forceinline__ void bj_apply(const double* __restrict__ m6, const double* r,
@@ -139,7 +128,8 @@ __global__ __launch_bounds__(kThreads) void k_init_state(CgState* st, const doub
     st->pq = 0.0;
     st->iter = 0;
     st->max_iter = max_iter;
-    st->arrive = 0;
+    st->iter_next = 0;
+    st->rz_prev = 0.0;
     if (bb == 0.0 || rr < st->tol2bb) {
       st->done = 1;
     } else if (!(rz > 0.0)) {
@@ -150,10 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_init_state(CgState* st, const doub
   }
 }
 
-// <p, q> partials; the last workgroup sets alpha (nrb == gridDim.x).
+// Partial slots: ||r||^2 at [0, nrb), <r, z> at [nrb, 2 nrb), <p, q> at [2 nrb, 3 nrb).
+// <p, q> partials.
 __global__ __launch_bounds__(kThreads) void k_dot_pq(const double* __restrict__ p,
                                                      const double* __restrict__ q, int64_t n,
-                                                     double* partial, CgState* st, int nrb) {
+                                                     double* partial, const CgState* st,
+                                                     int nrb) {
   __shared__ double sh[kThreads / 64];
   if (st->done) return;
   double v = 0.0;
@@ -161,49 +153,37 @@ __global__ __launch_bounds__(kThreads) void k_dot_pq(const double* __restrict__ 
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     v += p[i] * q[i];
   const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  if (!last_to_arrive(&st->arrive)) return;
-  const double pq = reduce_partials(partial, nrb, sh);
-  if (threadIdx.x == 0) {
-    st->pq = pq;
-    if (!(pq > 0.0)) {
-      st->done = 2;
-    } else {
-      st->alpha = st->rz / pq;
-    }
-  }
+  if (threadIdx.x == 0) partial[2 * nrb + blockIdx.x] = s;
 }
 
-// The stop test and beta from the ||r||^2 and <r, z> partials (one workgroup).
-__device__ __forceinline__ void finish_iteration(CgState* st, const double* partial, int nrb,
-                                                 double* sh) {
-  const double rr = reduce_partials(partial, nrb, sh);
-  const double rz = reduce_partials(partial + nrb, nrb, sh);
-  if (threadIdx.x == 0) {
-    st->iter += 1;
-    st->rr = rr;
-    if (rr < st->tol2bb) {
-      st->done = 1;
-    } else if (st->iter >= st->max_iter) {
-      st->done = 3;
-    } else if (!(rz > 0.0)) {
-      st->done = 2;
-    } else {
-      st->beta = rz / st->rz;
-      st->rz = rz;
-    }
-  }
-}
-
-template <bool kFinish>
+// alpha = <r, z> / <p, q> from the <p, q> partials, then x += alpha p, r -= alpha q,
+// z = M_BD r, q = 0, with the partials of ||r||^2 and <r, z>.
 __global__ __launch_bounds__(kThreads) void k_update(const double* __restrict__ minv, double* x,
                                                      double* r, double* z,
                                                      const double* __restrict__ p, double* q,
                                                      int64_t n_kept, double* partial, int nrb,
                                                      CgState* st) {
   __shared__ double sh[kThreads / 64];
+  __shared__ double s_pq;
   if (st->done) return;
-  const double alpha = st->alpha;
+  const double pq0 = reduce_partials(partial + 2 * nrb, nrb, sh);
+  if (threadIdx.x == 0) s_pq = pq0;
+  __syncthreads();
+  const double pq = s_pq;
+  if (!(pq > 0.0)) {  // the same test in every workgroup
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->pq = pq;
+      st->done = 2;
+    }
+    return;
+  }
+  const double alpha = st->rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->pq = pq;
+    st->alpha = alpha;
+    st->rz_prev = st->rz;
+    st->iter_next = st->iter + 1;
+  }
   double rr = 0.0, rz = 0.0;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n_kept;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
@@ -228,21 +208,46 @@ __global__ __launch_bounds__(kThreads) void k_update(const double* __restrict__ 
     partial[blockIdx.x] = s0;
     partial[nrb + blockIdx.x] = s1;
   }
-  if constexpr (kFinish) {
-    if (last_to_arrive(&st->arrive)) finish_iteration(st, partial, nrb, sh);
-  }
 }
 
-__global__ __launch_bounds__(kThreads) void k_beta(CgState* st, const double* partial, int nrb) {
-  __shared__ double sh[kThreads / 64];
-  if (st->done) return;
-  finish_iteration(st, partial, nrb, sh);
-}
-
+// The stop test and beta = <r', z'> / <r, z> from the ||r||^2 and <r, z> partials, then
+// p = z + beta p.  Workgroup 0 writes the iteration's outcome; a workgroup that starts after it
+// has set `done` skips, as it would have after the same test.
 __global__ __launch_bounds__(kThreads) void k_direction(const double* __restrict__ z, double* p,
-                                                        int64_t n, const CgState* st) {
+                                                        int64_t n, const double* partial,
+                                                        int nrb, CgState* st) {
+  __shared__ double sh[kThreads / 64];
+  __shared__ double s_rr, s_rz;
   if (st->done) return;
-  const double beta = st->beta;
+  const double rr0 = reduce_partials(partial, nrb, sh);
+  const double rz0 = reduce_partials(partial + nrb, nrb, sh);
+  if (threadIdx.x == 0) {
+    s_rr = rr0;
+    s_rz = rz0;
+  }
+  __syncthreads();
+  const double rr = s_rr, rz = s_rz;
+  const int iter = st->iter_next;
+  int done = 0;
+  if (rr < st->tol2bb) {
+    done = 1;
+  } else if (iter >= st->max_iter) {
+    done = 3;
+  } else if (!(rz > 0.0)) {
+    done = 2;
+  }
+  const double beta = done ? 0.0 : rz / st->rz_prev;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->iter = iter;
+    st->rr = rr;
+    if (done) {
+      st->done = done;
+    } else {
+      st->beta = beta;
+      st->rz = rz;
+    }
+  }
+  if (done) return;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     p[i] = z[i] + beta * p[i];
@@ -317,16 +322,12 @@ mm_status iteration(Plan* P, Work& W, double* x, bool two_level, hipStream_t s) 
   TimedLaunch tl(P, K_CG, s);
   hipLaunchKernelGGL(k_dot_pq, dim3(nrb), dim3(kThreads), 0, s, W.p, W.q, 3 * nk, W.partial,
                      W.state, nrb);
-  if (two_level) {
-    hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z,
-                       W.p, W.q, nk, W.partial, nrb, W.state);
-    MM_TRY(deflation_apply(P, W.r, W.z, nullptr, W.partial, nrb, done, s));
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(kThreads), 0, s, W.state, W.partial, nrb);
-  } else {
-    hipLaunchKernelGGL(k_update<true>, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z,
-                       W.p, W.q, nk, W.partial, nrb, W.state);
-  }
-  hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, W.z, W.p, 3 * nk, W.state);
+  hipLaunchKernelGGL(k_update, dim3(nrb), dim3(kThreads), 0, s, P->minv, x, W.r, W.z, W.p, W.q,
+                     nk, W.partial, nrb, W.state);
+  // z = M_2lvl r and its <r, z> partials replace those of the block-Jacobi z
+  if (two_level) MM_TRY(deflation_apply(P, W.r, W.z, nullptr, W.partial, nrb, done, s));
+  hipLaunchKernelGGL(k_direction, dim3(nrb), dim3(kThreads), 0, s, W.z, W.p, 3 * nk, W.partial,
+                     nrb, W.state);
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
 }

@@ -79,7 +79,8 @@ struct CgState {
   int32_t iter;
   int32_t done;     // 0 running, 1 converged, 2 breakdown, 3 iteration limit
   int32_t max_iter;
-  int32_t arrive;   // workgroups that have written their partials (zero between kernels)
+  int32_t iter_next;  // number of the iteration being completed (set with alpha)
+  double rz_prev;     // <r, z> before the update (set with alpha), beta's denominator
 };
 
 enum KernelKind { K_UNPOINT = 0, K_TOEPLITZ = 1, K_POINT = 2, K_CG = 3, K_NKINDS = 4 };
