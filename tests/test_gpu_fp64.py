@@ -74,6 +74,10 @@ CASES = {
     "fused_2e14": (lambda: synth.make_ground(cfg_id=99, n_dets=2, samples_per_det=70001,
                                              interval=30011, side=24, lam=4097),
                    {"fft_size": 1 << 14}),
+    # one sample per pixel: every wavefront round overflows the 64-run list of the scatter
+    "fused_2e15_dwell1": (lambda: synth.make_ground(cfg_id=101, n_dets=2, samples_per_det=70001,
+                                                    interval=65536, side=24, dwell=1, lam=8192,
+                                                    flag_frac=0.01), {}),
 }
 
 _cache = {}

@@ -45,6 +45,12 @@ CASES = {
     # 13 segments per block, the last one ragged
     "lam8192_long_blocks": (dict(cfg_id=47, n_dets=2, samples_per_det=200003, interval=200003,
                                  side=40, lam=8192, flag_frac=0.01), {}),
+    # one and three samples per pixel: 170 to 512 runs per wavefront and scatter round, more than
+    # the 64 the run list holds (the rest are flushed directly)
+    "lam8192_dwell1": (dict(cfg_id=49, n_dets=2, samples_per_det=100003, interval=50021, side=40,
+                            dwell=1, lam=8192, flag_frac=0.01), {}),
+    "lam8192_dwell3": (dict(cfg_id=50, n_dets=2, samples_per_det=100003, interval=50021, side=40,
+                            dwell=3, lam=8192, flag_frac=0.01), {}),
 }
 
 _cache = {}
