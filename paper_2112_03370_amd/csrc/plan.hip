@@ -39,6 +39,13 @@ struct BjFlush {
     for (int c = 0; c < 6; ++c) unsafeAtomicAdd(dst + c, v[c]);
     atomicAdd(hits + key, static_cast<int32_t>(v[6] + 0.5));
   }
+  __device__ void one(int key, int c, double v) const {
+    if (c < 6) {
+      unsafeAtomicAdd(B + 6 * static_cast<int64_t>(key) + c, v);
+    } else {
+      atomicAdd(hits + key, static_cast<int32_t>(v + 0.5));
+    }
+  }
 };
 
 __global__ __launch_bounds__(kThreads) void k_plan_accumulate(
@@ -103,7 +110,8 @@ __global__ __launch_bounds__(kThreads) void k_plan_accumulate(
         v[j][6] = 1.0;
       }
     }
-    wave_merge_runs_listed<kAccLane, 7, kAccListed>(key, v, flush, skey[wave], sval[wave]);
+    wave_merge_runs_listed<kAccLane, 7, kAccListed, BjFlush, true>(key, v, flush, skey[wave],
+                                                                  sval[wave]);
   }
 }
 
