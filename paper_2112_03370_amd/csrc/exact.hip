@@ -276,6 +276,11 @@ __global__ __launch_bounds__(kXThreads) void k_x_scatter(
     const double2* __restrict__ G, const int32_t* __restrict__ lpix,
     const float* __restrict__ wq, const float* __restrict__ wu, const Chunk* __restrict__ chunks,
     int seg0, int lam, int NC, double inv_n, double* __restrict__ y) {
+  // per wavefront: the runs it completes, listed before the atomics (one value per lane)
+  constexpr int kScatterListed = 64;
+  __shared__ int skey[kXThreads / 64][kScatterListed];
+  __shared__ double sval[kXThreads / 64][3 * kScatterListed];
+  const int wave = static_cast<int>(threadIdx.x >> 6);
   const Chunk c = chunks[seg0 + blockIdx.y];
   const int64_t base = static_cast<int64_t>(blockIdx.y) * NC;
   const int j0 = 4 * (blockIdx.x * kXThreads + threadIdx.x);
@@ -300,7 +305,8 @@ __global__ __launch_bounds__(kXThreads) void k_x_scatter(
       }
     }
   }
-  wave_merge_runs<3>(key, v, XFlush{y});
+  wave_merge_runs_listed<4, 3, kScatterListed, XFlush, true>(key, v, XFlush{y}, skey[wave],
+                                                             sval[wave]);
 }
 
 // ---- direct product for short bands (direct plans) ---------------------------------------
