@@ -478,8 +478,14 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
   // after every iteration and nothing is captured
   const bool one_by_one = P->precision == MM_PRECISION_FP64 && P->lambda_max > 0;
   int chunk = one_by_one ? 1 : (prm.check_every > 0 ? prm.check_every : 4);
+  // Graphs of `chunk` iterations are kept in the workspace and replayed by later solves with the
+  // same solution vector: capturing and instantiating one costs more than a tiny solve's eager
+  // launches, so a key's first chunk runs eagerly and its second use captures the graph.
+  // A workspace without a cache captures every time and destroys its graphs on return.
   const bool use_graph = prm.use_graph && !P->timing.enabled && !one_by_one;
-  hipGraphExec_t gexec = nullptr;
+  const uint64_t defl_gen = prm.two_level ? P->defl.gen : 0;
+  hipGraphExec_t gexec = nullptr;  // the graph being replayed (null: eager launches)
+  hipGraphExec_t owned = nullptr;  // instantiated here and not cached
   int graph_chunk = 0;
   struct GraphGuard {
     hipGraphExec_t* e;
@@ -489,7 +495,33 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
         (void)hipGraphExecDestroy(*e);
       }
     }
-  } gg{&gexec};
+  } gg{&owned};
+  auto capture = [&](hipGraphExec_t* out) -> mm_status {
+    hipGraph_t graph = nullptr;
+    std::shared_lock<std::shared_mutex> gate(alloc_gate());
+    MM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    mm_status st = MM_OK;
+    for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, prm.two_level, s);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    gate.unlock();
+    if (st != MM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (ce != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    hipError_t ie;
+    {
+      // instantiation may allocate device memory: keep it apart from other captures
+      std::unique_lock<std::shared_mutex> lock(alloc_gate());
+      ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+    }
+    if (ie != hipSuccess) {
+      *out = nullptr;
+      return fail(MM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    return MM_OK;
+  };
   int queued = 0;
   const int32_t tag_base = P->timing.next_tag;
   while (true) {
@@ -497,36 +529,50 @@ mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStre
     MM_HIP_TRY(hipStreamSynchronize(s));
     if (W.h_state->done) break;
     if (queued >= prm.max_iter + 1) break;  // safety: the device stops at max_iter
-    if (use_graph) {
-      if (gexec == nullptr || graph_chunk != chunk) {
-        if (gexec) {
+    // the stream is idle from here to the launches below: a graph destroyed or evicted here
+    // is not in flight
+    if (use_graph && graph_chunk != chunk) {
+      gexec = nullptr;
+      graph_chunk = chunk;
+      if (W.cache_graphs) {
+        GraphSlot* hit = nullptr;
+        for (GraphSlot& g : W.graphs)
+          if (g.used && g.x == x && g.chunk == chunk && g.two_level == prm.two_level &&
+              g.defl_gen == defl_gen)
+            hit = &g;
+        if (hit == nullptr) {
+          // first use of this key: remember it (an unused slot, else the least recently used
+          // one) and run the chunk eagerly
+          hit = &W.graphs[0];
+          for (GraphSlot& g : W.graphs) {
+            if (!g.used) {
+              hit = &g;
+              break;
+            }
+            if (g.last_use < hit->last_use) hit = &g;
+          }
+          if (hit->exec) {
+            std::unique_lock<std::shared_mutex> lock(alloc_gate());
+            (void)hipGraphExecDestroy(hit->exec);
+          }
+          *hit = GraphSlot{true, nullptr, x, chunk, prm.two_level, defl_gen, ++W.graph_clock};
+        } else {
+          if (hit->exec == nullptr) MM_TRY(capture(&hit->exec));
+          hit->last_use = ++W.graph_clock;
+          gexec = hit->exec;
+        }
+      } else {
+        if (owned) {
           std::unique_lock<std::shared_mutex> lock(alloc_gate());
-          const hipError_t de = hipGraphExecDestroy(gexec);
-          gexec = nullptr;
+          const hipError_t de = hipGraphExecDestroy(owned);
+          owned = nullptr;
           if (de != hipSuccess) return fail(MM_ERR_HIP, std::string("graph destroy: ") + hipGetErrorString(de));
         }
-        hipGraph_t graph = nullptr;
-        std::shared_lock<std::shared_mutex> gate(alloc_gate());
-        MM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        mm_status st = MM_OK;
-        for (int i = 0; i < chunk && st == MM_OK; ++i) st = iteration(P, W, x, prm.two_level, s);
-        hipError_t ce = hipStreamEndCapture(s, &graph);
-        gate.unlock();
-        if (st != MM_OK) {
-          if (graph) (void)hipGraphDestroy(graph);
-          return st;
-        }
-        if (ce != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-        hipError_t ie;
-        {
-          // instantiation may allocate device memory: keep it apart from other captures
-          std::unique_lock<std::shared_mutex> lock(alloc_gate());
-          ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(graph);
-        }
-        if (ie != hipSuccess) return fail(MM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        graph_chunk = chunk;
+        MM_TRY(capture(&owned));
+        gexec = owned;
       }
+    }
+    if (gexec != nullptr) {
       MM_HIP_TRY(hipGraphLaunch(gexec, s));
     } else {
       for (int i = 0; i < chunk; ++i) {

@@ -13,6 +13,7 @@
 //   s = Z^T r (k_defl_dots: per-workgroup partials for 8 columns at a time),
 //   c = E^+ s (k_defl_coef: one workgroup),
 //   z = M_BD (r - Z' c) + Z c  and the partial sums of <r, z> (k_defl_apply).
+#include <atomic>
 #include <chrono>
 #include <cmath>
 
@@ -336,6 +337,8 @@ mm_status deflation_build(Plan* P, const float* d, int32_t m, hipStream_t s) {
                             hipMemcpyHostToDevice, s));
   MM_HIP_TRY(hipStreamSynchronize(s));
   D.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  static std::atomic<uint64_t> builds{0};
+  D.gen = ++builds;
   guard.keep = true;
   P->defl = D;
   return MM_OK;

@@ -103,6 +103,20 @@ struct Timing {
 // Per-solve device workspace: time-domain buffers (unfused and direct products), long-segment
 // tiles, the PCG vectors and scalars.  A plan holds one for the plain calls; a server gives every
 // running request its own, so that solves on one plan can overlap.
+// An instantiated graph of `chunk` PCG iterations, as captured for one solution vector and
+// deflation space (the plan and workspace buffers are fixed for the workspace's life).  A key
+// seen once holds no graph yet: its first chunk runs eagerly, the next use captures it.
+struct GraphSlot {
+  bool used = false;
+  hipGraphExec_t exec = nullptr;
+  const double* x = nullptr;
+  int32_t chunk = 0;
+  bool two_level = false;
+  uint64_t defl_gen = 0;
+  uint64_t last_use = 0;
+};
+constexpr int kGraphSlots = 8;
+
 struct Work {
   float* t = nullptr;           // [n_samples] (only when the product is not fused)
   float* u = nullptr;
@@ -117,6 +131,11 @@ struct Work {
   CgState* state = nullptr;
   CgState* h_state = nullptr;   // pinned host mirror
   int64_t bytes = 0;
+  // Iteration graphs kept across solves (workspaces from work_alloc; they are destroyed with
+  // the workspace).  A workspace runs one solve at a time, always with the same plan.
+  bool cache_graphs = false;
+  GraphSlot graphs[kGraphSlots];
+  uint64_t graph_clock = 0;
 };
 
 // Two-level preconditioner state (deflation.hip): Lanczos basis V_m (Z), the stored products
@@ -135,6 +154,7 @@ struct Deflation {
   double* einv = nullptr;      // [m][m]
   double* partial = nullptr;   // dot partials
   double* c = nullptr;         // [kMaxDeflation] coefficients + scalars
+  uint64_t gen = 0;            // unique per build (0: none); keys the cached iteration graphs
 };
 
 struct Plan;

@@ -749,11 +749,17 @@ mm_status work_alloc(const Plan* P, Work* W) {
     MM_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&W->h_state), sizeof(CgState),
                              hipHostMallocDefault));
   }
+  W->cache_graphs = true;
   guard.keep = true;
   return MM_OK;
 }
 
 void work_free(Work* W) {
+  {
+    std::unique_lock<std::shared_mutex> lock(alloc_gate());
+    for (GraphSlot& g : W->graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  }
   void* ptrs[] = {W->t, W->u, W->scratch, W->r, W->z, W->p, W->q, W->b, W->partial, W->state};
   for (void* p : ptrs) dev_free(p);
   if (W->h_state) {

@@ -59,6 +59,11 @@ CASES = {
                                            interval=1 << 16, side=32, lam=8192), {}),
     "fft_2e17": (lambda: synth.make_ground(cfg_id=96, n_dets=2, samples_per_det=1 << 18,
                                            interval=3 << 16, side=32, lam=20000), {}),
+    # the batched transform's scatter with one sample per pixel: more runs per wavefront than
+    # its 64-run list holds
+    "fft_2e17_dwell1": (lambda: synth.make_ground(cfg_id=102, n_dets=2, samples_per_det=1 << 18,
+                                                  interval=3 << 16, side=32, dwell=1, lam=20000,
+                                                  flag_frac=0.01), {}),
     # 2^16 points: one radix-256 pass, one radix-16 pass and one radix-8 pass per transform
     "fft_2e16": (lambda: synth.make_ground(cfg_id=100, n_dets=2, samples_per_det=150001,
                                            interval=70001, side=32, lam=12001, flag_frac=0.01),

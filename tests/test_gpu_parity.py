@@ -302,6 +302,35 @@ def test_pcg_graph_and_eager_agree(gpu_lib):
     assert err <= 1e-8, err
 
 
+def test_cached_graphs_replay_across_solves(gpu_lib):
+    # The iteration graphs stay in the plan's workspace and are replayed by later solves into
+    # the same map buffer: other right-hand sides, and a two-level solve after the deflation
+    # space was rebuilt (its graph must be captured anew).  Every replay is compared with an
+    # eager solve run between the replays.
+    prob, ref = case("tiny")
+    plan = _plan(gpu_lib, prob)
+    torch = _torch()
+    d0 = prob.d[0]
+    d1 = (0.5 * d0 + np.random.default_rng(5).standard_normal(d0.size)).astype(np.float32)
+    X = torch.zeros(ref.n_kept, 3, dtype=torch.float64, device="cuda")
+    for d in (d0, d1, d0, d1):
+        xg, ig = plan.pcg_solve(_dev(d), x=X)
+        xg = xg.cpu().numpy().copy()
+        xe, ie = plan.pcg_solve(_dev(d), use_graph=False)
+        assert ig["converged"] == 1 and ig["iterations"] == ie["iterations"]
+        err = float(_rel(xg, xe.cpu().numpy()))
+        assert err <= 1e-8, err
+    for m in (8, 12):
+        plan.deflation_build(_dev(d0), m)
+        for d in (d1, d0):
+            xg, ig = plan.pcg_solve(_dev(d), x=X, precond=1)
+            xg = xg.cpu().numpy().copy()
+            xe, ie = plan.pcg_solve(_dev(d), use_graph=False, precond=1)
+            assert ig["converged"] == 1 and ig["iterations"] == ie["iterations"], (m, ig, ie)
+            err = float(_rel(xg, xe.cpu().numpy()))
+            assert err <= 1e-8, (m, err)
+
+
 def test_white_noise_binned_map_in_one_iteration(gpu_lib):
     prob = synth.make_raster(cfg_id=52, n_dets=3, side=16, dwell=4, lam=0, noise="white")
     ref = O.plan_from_problem(prob)
