@@ -645,15 +645,23 @@ struct DevVec {
 // FP64; inner PCG with the plan's own product on A dx = r to the relative tolerance that
 // brings ||r|| under tol ||b|| with a factor 2 to spare; x += dx.  Stops when the FP64
 // residual is below tol.  *rel64 is the FP64 relative residual of the returned x.
+// r = b - A x in FP64 (Eq. CGresidual), and refinement steps on it.  Where the FP64 product
+// takes the time-domain residual, r = P^T N^-1 (d - P x) is one product (no cancellation
+// between two large vectors) and ||b|| is that of the solve's right-hand side (its FP32
+// time-domain rounding moves the ratio by ~1e-7 of itself); otherwise r is the FP64
+// right-hand side minus the FP64 product, relative to the FP64 right-hand side.
 mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgParams& outer,
-                      int32_t max_steps, hipStream_t s, double* rel64, int32_t* steps,
-                      int32_t* inner_its) {
+                      int32_t max_steps, double bb_solve, hipStream_t s, double* rel64,
+                      int32_t* steps, int32_t* inner_its) {
   const int64_t nu = 3 * P->n_kept;
+  const bool one_product = exact_residual_supported(P);
   DevVec<double> b64, dx;
-  MM_TRY(b64.alloc(static_cast<size_t>(nu)));
-  MM_TRY(exact_product(P, nullptr, d, b64.p, s));
-  double bb = 0.0;
-  MM_TRY(sub_norm2(W, b64.p, nullptr, nullptr, nu, &bb, s));
+  double bb = bb_solve;
+  if (!one_product) {
+    MM_TRY(b64.alloc(static_cast<size_t>(nu)));
+    MM_TRY(exact_product(P, nullptr, d, b64.p, s));
+    MM_TRY(sub_norm2(W, b64.p, nullptr, nullptr, nu, &bb, s));
+  }
   *steps = 0;
   *inner_its = 0;
   if (!(bb > 0.0)) {
@@ -662,9 +670,14 @@ mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgPara
   }
   if (max_steps > 0) MM_TRY(dx.alloc(static_cast<size_t>(nu)));
   while (true) {
-    MM_TRY(exact_product(P, x, nullptr, W.q, s));
     double rr = 0.0;
-    MM_TRY(sub_norm2(W, b64.p, W.q, W.b, nu, &rr, s));  // W.b = r = b - A x
+    if (one_product) {
+      MM_TRY(exact_product(P, x, d, W.b, s));  // W.b = r = P^T N^-1 (d - P x)
+      MM_TRY(sub_norm2(W, W.b, nullptr, nullptr, nu, &rr, s));
+    } else {
+      MM_TRY(exact_product(P, x, nullptr, W.q, s));
+      MM_TRY(sub_norm2(W, b64.p, W.q, W.b, nu, &rr, s));  // W.b = r = b - A x
+    }
     *rel64 = std::sqrt(rr / bb);
     if (*rel64 < outer.tol || *steps >= max_steps) break;
     PcgParams inner = outer;
@@ -723,13 +736,13 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
   const bool fp64_products = P->precision == MM_PRECISION_FP64 || P->lambda_max == 0;
   if (opts.refine > 0 && st.bb > 0.0) {
     if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
-    MM_TRY(refine_fp64(P, W, d, x, prm, opts.refine, s, &rel64, &steps, &inner_its));
+    MM_TRY(refine_fp64(P, W, d, x, prm, opts.refine, st.bb, s, &rel64, &steps, &inner_its));
   } else if (opts.check_fp64 && st.bb > 0.0) {
     if (fp64_products) {
       rel64 = std::sqrt(true_rr / st.bb);  // the products are FP64 already
     } else {
       if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
-      MM_TRY(refine_fp64(P, W, d, x, prm, 0, s, &rel64, &steps, &inner_its));
+      MM_TRY(refine_fp64(P, W, d, x, prm, 0, st.bb, s, &rel64, &steps, &inner_its));
     }
   } else if (opts.refine > 0 || opts.check_fp64) {
     rel64 = 0.0;  // b = 0

@@ -120,8 +120,13 @@ __device__ __forceinline__ double2 tw_n(const double2* __restrict__ tw, int k, i
   return make_double2(-t.x, -t.y);
 }
 
+// What the FP64 product gathers as its time stream: P x (kInMap), the data d (kInData), or the
+// time-domain residual d - P x (kInResid; zero at flagged samples as d is), so that one product
+// gives P^T N^-1 (d - P x) = b - A x without the cancellation of two large products.
+enum : int { kInMap = 0, kInData = 1, kInResid = 2 };
+
 // ---- load: window samples of each segment, packed as complex points -----------------------
-template <bool kData>
+template <int kIn>
 __global__ __launch_bounds__(kXThreads) void k_x_load(
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
     const double* __restrict__ x, const float* __restrict__ d, const Chunk* __restrict__ chunks,
@@ -138,11 +143,12 @@ __global__ __launch_bounds__(kXThreads) void k_x_load(
     if (g >= b0 && g < b1) {
       const int p = lpix[g];
       if (p >= 0) {
-        if (kData) {
+        if constexpr (kIn == kInData) {
           t = static_cast<double>(d[g]);
         } else {
           const double* m = x + 3 * static_cast<int64_t>(p);
           t = m[0] + static_cast<double>(wq[g]) * m[1] + static_cast<double>(wu[g]) * m[2];
+          if constexpr (kIn == kInResid) t = static_cast<double>(d[g]) - t;
         }
       }
     }
@@ -493,15 +499,16 @@ __device__ __forceinline__ void xfft(double2 (&v)[16], double* sh, int t, bool p
 // g a multiple of 4: the pointing comes in 16-byte loads, and scan runs keep a pixel for several
 // samples, so the pixel values of the lane's first and last samples are loaded together and a
 // third pixel only when one occurs.  The sums are those of the one-sample form.
-template <bool kData>
+template <int kIn>
 __device__ __forceinline__ void xgather8(const int32_t* __restrict__ lpix,
                                          const float* __restrict__ wq,
                                          const float* __restrict__ wu,
                                          const double* __restrict__ x,
                                          const float* __restrict__ d, int64_t g,
                                          double (&o)[8]) {
+  constexpr bool kData = kIn == kInData;
   int kk[8];
-  float qq[8], uu[8];
+  float qq[8], uu[8], dd[8];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int4 k4 = *reinterpret_cast<const int4*>(lpix + g + 4 * c);
@@ -520,6 +527,13 @@ __device__ __forceinline__ void xgather8(const int32_t* __restrict__ lpix,
       uu[4 * c + 1] = u4.y;
       uu[4 * c + 2] = u4.z;
       uu[4 * c + 3] = u4.w;
+    }
+    if constexpr (kIn == kInResid) {
+      const float4 d4 = *reinterpret_cast<const float4*>(d + g + 4 * c);
+      dd[4 * c] = d4.x;
+      dd[4 * c + 1] = d4.y;
+      dd[4 * c + 2] = d4.z;
+      dd[4 * c + 3] = d4.w;
     }
   }
   if constexpr (kData) {
@@ -560,10 +574,15 @@ __device__ __forceinline__ void xgather8(const int32_t* __restrict__ lpix,
         }
       }
     }
+    if constexpr (kIn == kInResid) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (kk[j] >= 0) o[j] = static_cast<double>(dd[j]) - o[j];
+    }
   }
 }
 
-template <int M, bool kData>
+template <int M, int kIn>
 __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
     const int32_t* __restrict__ lpix, const float* __restrict__ wq, const float* __restrict__ wu,
     const double* __restrict__ x, const float* __restrict__ d, int dvec,
@@ -588,8 +607,8 @@ __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
       const int n = 8 * (t + r * T);  // sample of the half
       const int64_t g = c.out0 - lam + static_cast<int64_t>(h) * NC + n;
       double o[8];
-      if (g >= b0 && g + 8 <= b1 && (g & 3) == 0 && (!kData || dvec)) {
-        xgather8<kData>(lpix, wq, wu, x, d, g, o);
+      if (g >= b0 && g + 8 <= b1 && (g & 3) == 0 && (kIn == kInMap || dvec)) {
+        xgather8<kIn>(lpix, wq, wu, x, d, g, o);
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -598,11 +617,12 @@ __global__ __launch_bounds__(XFused<M>::T) void k_x_fused(
           if (gj >= b0 && gj < b1) {
             const int p = lpix[gj];
             if (p >= 0) {
-              if (kData) {
+              if constexpr (kIn == kInData) {
                 val = static_cast<double>(d[gj]);
               } else {
                 const double* m = x + 3 * static_cast<int64_t>(p);
                 val = m[0] + static_cast<double>(wq[gj]) * m[1] + static_cast<double>(wu[gj]) * m[2];
+                if constexpr (kIn == kInResid) val = static_cast<double>(d[gj]) - val;
               }
             }
           }
@@ -776,13 +796,17 @@ mm_status launch_fused_m(Plan* P, const double* x, const float* d, double* y, hi
   const double inv_n = 1.0 / static_cast<double>(P->fft_n);
   const int dvec = (reinterpret_cast<uintptr_t>(d) & 15u) == 0 ? 1 : 0;
   if (x == nullptr)
-    hipLaunchKernelGGL((k_x_fused<M, true>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s, P->lpix,
-                       P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec, P->x_tw,
-                       inv_n, y);
+    hipLaunchKernelGGL((k_x_fused<M, kInData>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s,
+                       P->lpix, P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec,
+                       P->x_tw, inv_n, y);
+  else if (d == nullptr)
+    hipLaunchKernelGGL((k_x_fused<M, kInMap>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s,
+                       P->lpix, P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec,
+                       P->x_tw, inv_n, y);
   else
-    hipLaunchKernelGGL((k_x_fused<M, false>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s, P->lpix,
-                       P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec, P->x_tw,
-                       inv_n, y);
+    hipLaunchKernelGGL((k_x_fused<M, kInResid>), dim3(P->n_chunks), dim3(XFused<M>::T), 0, s,
+                       P->lpix, P->wq, P->wu, x, d, dvec, P->chunks, P->lambda_max, P->x_spec,
+                       P->x_tw, inv_n, y);
   MM_HIP_TRY(hipGetLastError());
   return MM_OK;
 }
@@ -868,7 +892,14 @@ mm_status prepare(Plan* P, hipStream_t s) {
 
 }  // namespace
 
+bool exact_residual_supported(const Plan* P) {
+  return P->n_poly == 0 && P->lambda_max > 0 && P->algo == MM_TOEPLITZ_FFT &&
+         P->n_id_tiles == 0;
+}
+
 mm_status exact_product(Plan* P, const double* x, const float* d, double* y, hipStream_t s) {
+  if (x != nullptr && d != nullptr && !exact_residual_supported(P))
+    return fail(MM_ERR_UNSUPPORTED, "FP64 residual product: Toeplitz FFT plans only");
   MM_TRY(launch_zero(y, 3 * P->n_kept, s));
   if (P->n_kept == 0) return MM_OK;
   const bool data = x == nullptr;
@@ -901,11 +932,14 @@ mm_status exact_product(Plan* P, const double* x, const float* d, double* y, hip
       const int nseg = std::min(batch, P->n_chunks - seg0);
       const dim3 gpts((NC + kXThreads - 1) / kXThreads, nseg);
       if (data)
-        hipLaunchKernelGGL(k_x_load<true>, gpts, dim3(kXThreads), 0, s, P->lpix, P->wq, P->wu,
-                           x, d, P->chunks, seg0, lam, NC, ta.p);
+        hipLaunchKernelGGL(k_x_load<kInData>, gpts, dim3(kXThreads), 0, s, P->lpix, P->wq,
+                           P->wu, x, d, P->chunks, seg0, lam, NC, ta.p);
+      else if (d == nullptr)
+        hipLaunchKernelGGL(k_x_load<kInMap>, gpts, dim3(kXThreads), 0, s, P->lpix, P->wq,
+                           P->wu, x, d, P->chunks, seg0, lam, NC, ta.p);
       else
-        hipLaunchKernelGGL(k_x_load<false>, gpts, dim3(kXThreads), 0, s, P->lpix, P->wq, P->wu,
-                           x, d, P->chunks, seg0, lam, NC, ta.p);
+        hipLaunchKernelGGL(k_x_load<kInResid>, gpts, dim3(kXThreads), 0, s, P->lpix, P->wq,
+                           P->wu, x, d, P->chunks, seg0, lam, NC, ta.p);
       MM_HIP_TRY(hipGetLastError());
       double2* spec_in = nullptr;
       MM_TRY(batch_fft(ta.p, tb.p, P->x_tw, NC, nseg, s, &spec_in));

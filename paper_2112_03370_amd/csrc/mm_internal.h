@@ -338,9 +338,11 @@ mm_status deflation_apply(Plan* P, const double* r, double* z, double* p, double
 
 // FP64 band symbols at the plan's FFT length (plan.hip).
 mm_status launch_band_symbol64(Plan* P, double* spec64, hipStream_t s);
-// FP64 product (exact.hip): y = P^T N^-1 P x (d == nullptr) or y = P^T N^-1 d (x == nullptr),
-// every step in FP64, y overwritten.  Synchronous (staging tiles are allocated per call).
+// FP64 product (exact.hip): y = P^T N^-1 P x (d == nullptr), y = P^T N^-1 d (x == nullptr) or,
+// with both, y = P^T N^-1 (d - P x) = b - A x (plans with exact_residual_supported only), every
+// step in FP64, y overwritten.  Synchronous (staging tiles are allocated per call).
 mm_status exact_product(Plan* P, const double* x, const float* d, double* y, hipStream_t s);
+bool exact_residual_supported(const Plan* P);
 
 // Template map-making (templates.hip): tables and kernel blocks at plan time (tiles: the
 // plan's weight tiles, sorted, covering every sample), and y += P^T F_T P x (d == nullptr) or
@@ -370,10 +372,11 @@ struct PcgParams {
 // to *out.  Synchronous.
 mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStream_t s,
                       CgState* out);
-// FP64 true residual and iterative refinement after a solve (cg.hip).
+// FP64 true residual and iterative refinement after a solve (cg.hip); bb_solve = ||b||^2 of
+// the solve's right-hand side.
 mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgParams& outer,
-                      int32_t max_steps, hipStream_t s, double* rel64, int32_t* steps,
-                      int32_t* inner_its);
+                      int32_t max_steps, double bb_solve, hipStream_t s, double* rel64,
+                      int32_t* steps, int32_t* inner_its);
 // ||W.b - A x||^2 with the plan's product (uses W.q and the partials).  Synchronous.
 mm_status residual_norm2(Plan* P, Work& W, const double* x, double* rr, hipStream_t s);
 
