@@ -293,11 +293,84 @@ __global__ __launch_bounds__(kTT) void k_template_apply(
   }
 }
 
-// Kernel blocks K_b = sum_s w_s T_s T_s^T (upper triangle, FP64), one workgroup per baseline.
+// Pseudo-inverse of a symmetric positive semi-definite NP x NP block by cyclic Jacobi rotations
+// (eigenvalues below rtol times the largest dropped), in registers: the same algorithm as the
+// host routine used for the block recurrences.
+template <int NP>
+__device__ __forceinline__ void small_sym_pinv(double (&a)[NP][NP], double (&v)[NP][NP],
+                                               double rtol, double (&out)[NP][NP]) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v[i][j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        tot += a[i][j] * a[i][j];
+        if (i != j) off += a[i][j] * a[i][j];
+      }
+    if (off <= 1e-30 * tot || tot == 0.0) break;
+#pragma unroll
+    for (int p = 0; p < NP - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < NP; ++q) {
+        const double apq = a[p][q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {  // columns p, q
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {  // rows p, q
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {  // eigenvectors
+          const double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = c * vkp - sn * vkq;
+          v[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  double wmax = 0.0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) wmax = fmax(wmax, a[i][i]);
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) out[i][j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const double w = a[e][e];
+    if (!(w > rtol * wmax) || w <= 0.0) continue;
+    const double inv = 1.0 / w;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) out[i][j] += v[i][e] * inv * v[j][e];
+  }
+}
+
+// Kernel block of one baseline, K = sum_j w T(j) T(j)^T over its unflagged samples (Legendre
+// templates T), and its pseudo-inverse (zero for a block of zeros), one workgroup per baseline:
+// every pair (i <= k) is accumulated in the same pass over the samples, reduced across the
+// workgroup, and the first thread inverts the block.
+template <int NP>
 __global__ __launch_bounds__(kTT) void k_template_kernel(const int32_t* __restrict__ lpix,
                                                          const TBase* __restrict__ bases,
-                                                         int n_poly, double* __restrict__ K) {
-  __shared__ double red[kTT / 64];
+                                                         double* __restrict__ Kinv) {
+  constexpr int NPAIR = NP * (NP + 1) / 2;
+  __shared__ double red[NPAIR][kTT / 64];
   __shared__ double scale[kMaxTemplates];
   const TBase B = bases[blockIdx.x];
   const int tid = threadIdx.x;
@@ -305,32 +378,58 @@ __global__ __launch_bounds__(kTT) void k_template_kernel(const int32_t* __restri
   if (tid < kMaxTemplates) scale[tid] = sqrt((2.0 * tid + 1.0) * invL);
   __syncthreads();
   const double w = static_cast<double>(B.w);
-  for (int i = 0; i < n_poly; ++i) {
-    for (int k = i; k < n_poly; ++k) {
-      double acc = 0.0;
-      for (int j = tid; j < B.len; j += kTT) {
-        if (lpix[B.start + j] < 0) continue;
-        double T[kMaxTemplates];
-        legendre<kMaxTemplates>(fma(2.0, static_cast<double>(j), 1.0) * invL - 1.0, scale, T);
-        double ti = 0.0, tk = 0.0;
+  double acc[NPAIR];
 #pragma unroll
-        for (int m = 0; m < kMaxTemplates; ++m) {
-          if (m == i) ti = T[m];
-          if (m == k) tk = T[m];
-        }
-        acc = fma(w * ti, tk, acc);
-      }
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
-      if ((tid & 63) == 0) red[tid >> 6] = acc;
-      __syncthreads();
-      if (tid == 0) {
-        double sum = 0.0;
-        for (int wv = 0; wv < kTT / 64; ++wv) sum += red[wv];
-        K[static_cast<int64_t>(blockIdx.x) * n_poly * n_poly + i * n_poly + k] = sum;
-      }
-      __syncthreads();
-    }
+  for (int q = 0; q < NPAIR; ++q) acc[q] = 0.0;
+  for (int j = tid; j < B.len; j += kTT) {
+    if (lpix[B.start + j] < 0) continue;
+    double T[NP];
+    legendre<NP>(fma(2.0, static_cast<double>(j), 1.0) * invL - 1.0, scale, T);
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int k = i; k < NP; ++k, ++q) acc[q] = fma(w * T[i], T[k], acc[q]);
   }
+#pragma unroll
+  for (int q = 0; q < NPAIR; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((tid & 63) == 0) red[q][tid >> 6] = v;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  // the rotations work in registers for up to five templates, in LDS beyond (register room)
+  constexpr bool kRegs = NP <= 5;
+  __shared__ double lds_g[kRegs ? 1 : NP][NP], lds_v[kRegs ? 1 : NP][NP],
+      lds_o[kRegs ? 1 : NP][NP];
+  double reg_g[kRegs ? NP : 1][NP], reg_v[kRegs ? NP : 1][NP], reg_o[kRegs ? NP : 1][NP];
+  auto& G = *reinterpret_cast<double(*)[NP][NP]>(kRegs ? &reg_g[0][0] : &lds_g[0][0]);
+  auto& V = *reinterpret_cast<double(*)[NP][NP]>(kRegs ? &reg_v[0][0] : &lds_v[0][0]);
+  auto& Gi = *reinterpret_cast<double(*)[NP][NP]>(kRegs ? &reg_o[0][0] : &lds_o[0][0]);
+  bool zero = true;
+  int q = 0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int k = i; k < NP; ++k, ++q) {
+      double sum = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kTT / 64; ++wv) sum += red[q][wv];
+      G[i][k] = G[k][i] = sum;
+      zero = zero && sum == 0.0;
+    }
+  double* out = Kinv + static_cast<int64_t>(blockIdx.x) * NP * NP;
+  if (zero) {
+#pragma unroll
+    for (int i = 0; i < NP * NP; ++i) out[i] = 0.0;
+    return;
+  }
+  small_sym_pinv<NP>(G, V, 1e-12, Gi);
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) out[i * NP + k] = Gi[i][k];
 }
 
 }  // namespace
@@ -432,32 +531,20 @@ mm_status build_templates(Plan* P, const mm_geometry* g, const std::vector<Tile>
     MM_HIP_TRY(hipStreamSynchronize(s));
     return MM_OK;
   }
-  // kernel blocks on the device, pseudo-inverses on the host
-  const size_t nk = bases.size() * static_cast<size_t>(n_poly * n_poly);
-  std::vector<double> hk(nk, 0.0);
-  MM_HIP_TRY(hipMemsetAsync(P->tkinv, 0, nk * sizeof(double), s));
-  hipLaunchKernelGGL(k_template_kernel, dim3(static_cast<unsigned>(bases.size())), dim3(kTT), 0, s,
-                     P->lpix, P->tbases, n_poly, P->tkinv);
-  MM_HIP_TRY(hipGetLastError());
-  MM_HIP_TRY(hipMemcpyAsync(hk.data(), P->tkinv, nk * sizeof(double), hipMemcpyDeviceToHost, s));
-  MM_HIP_TRY(hipStreamSynchronize(s));
-  std::vector<double> G(static_cast<size_t>(n_poly * n_poly)), Gi;
-  for (size_t b = 0; b < bases.size(); ++b) {
-    double* Kb = hk.data() + b * n_poly * n_poly;
-    for (int i = 0; i < n_poly; ++i)
-      for (int k = 0; k < n_poly; ++k)
-        G[static_cast<size_t>(i * n_poly + k)] = i <= k ? Kb[i * n_poly + k] : Kb[k * n_poly + i];
-    bool zero = true;
-    for (double v : G) zero = zero && v == 0.0;
-    if (zero) {
-      std::fill(Kb, Kb + n_poly * n_poly, 0.0);
-      continue;
-    }
-    sym_pinv(G, n_poly, 1e-12, Gi);
-    std::copy(Gi.begin(), Gi.end(), Kb);
+  // kernel blocks and their pseudo-inverses on the device, one workgroup per baseline
+  const dim3 grid(static_cast<unsigned>(bases.size()));
+  switch (n_poly) {
+    case 1: hipLaunchKernelGGL(k_template_kernel<1>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    case 2: hipLaunchKernelGGL(k_template_kernel<2>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    case 3: hipLaunchKernelGGL(k_template_kernel<3>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    case 4: hipLaunchKernelGGL(k_template_kernel<4>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    case 5: hipLaunchKernelGGL(k_template_kernel<5>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    case 6: hipLaunchKernelGGL(k_template_kernel<6>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    case 7: hipLaunchKernelGGL(k_template_kernel<7>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
+    default: hipLaunchKernelGGL(k_template_kernel<8>, grid, dim3(kTT), 0, s, P->lpix, P->tbases, P->tkinv); break;
   }
-  MM_HIP_TRY(hipMemcpyAsync(P->tkinv, hk.data(), nk * sizeof(double), hipMemcpyHostToDevice, s));
-  MM_HIP_TRY(hipStreamSynchronize(s));
+  MM_HIP_TRY(hipGetLastError());
+  MM_HIP_TRY(hipStreamSynchronize(s));  // the host tables above are released on return
   return MM_OK;
 }
 

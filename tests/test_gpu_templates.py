@@ -44,6 +44,11 @@ CASES = {
     "poly5_short": lambda: synth.make_templates(cfg_id=63, n_dets=4, samples_per_det=6000,
                                                 interval=3000, side=16, dwell=4, baseline=97,
                                                 n_poly=5, cover=0.85, flag_frac=0.05),
+    # eight templates: the kernel blocks' rotations run in LDS (160-sample baselines keep the
+    # blocks well conditioned, so the 1e-12 right-hand-side bound applies)
+    "poly8": lambda: synth.make_templates(cfg_id=65, n_dets=3, samples_per_det=6000,
+                                          interval=3000, side=16, dwell=4, baseline=160,
+                                          n_poly=8, cover=0.85, flag_frac=0.05),
     "offsets_full_cover": lambda: synth.make_templates(cfg_id=64, n_dets=3,
                                                        samples_per_det=1 << 14,
                                                        interval=1 << 13, side=24, dwell=8,
