@@ -331,6 +331,26 @@ def test_cached_graphs_replay_across_solves(gpu_lib):
             assert err <= 1e-8, (m, err)
 
 
+def test_cached_graphs_evicted_and_recaptured(gpu_lib):
+    # Ten map buffers, each solved into twice: thirty (buffer, chunk) keys pass through the
+    # workspace's eight graph slots, so graphs are evicted and captured again between solves;
+    # every solve must still equal an eager one.
+    prob, ref = case("tiny")
+    plan = _plan(gpu_lib, prob)
+    torch = _torch()
+    d = _dev(prob.d[0])
+    xe, ie = plan.pcg_solve(d, use_graph=False)
+    xe = xe.cpu().numpy()
+    bufs = [torch.zeros(ref.n_kept, 3, dtype=torch.float64, device="cuda") for _ in range(10)]
+    for rep in range(2):
+        for X in bufs:
+            X.zero_()
+            xg, ig = plan.pcg_solve(d, x=X)
+            assert ig["converged"] == 1 and ig["iterations"] == ie["iterations"], (rep, ig)
+            err = float(_rel(xg.cpu().numpy(), xe))
+            assert err <= 1e-8, (rep, err)
+
+
 def test_white_noise_binned_map_in_one_iteration(gpu_lib):
     prob = synth.make_raster(cfg_id=52, n_dets=3, side=16, dwell=4, lam=0, noise="white")
     ref = O.plan_from_problem(prob)
