@@ -493,13 +493,18 @@ namespace {
 // Stream-ordered upload (no legacy-stream operation: other threads may be capturing graphs on
 // their own streams meanwhile); synchronous, since h is released by the caller afterwards.
 template <class T>
-mm_status upload(Plan* P, T** dst, const std::vector<T>& h, hipStream_t s) {
-  MM_TRY(dalloc(P, dst, h.size()));
-  if (!h.empty()) {
-    MM_HIP_TRY(hipMemcpyAsync(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+mm_status upload(Plan* P, T** dst, const T* h, size_t n, hipStream_t s) {
+  MM_TRY(dalloc(P, dst, n));
+  if (n > 0) {
+    MM_HIP_TRY(hipMemcpyAsync(*dst, h, n * sizeof(T), hipMemcpyHostToDevice, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
   }
   return MM_OK;
+}
+
+template <class T>
+mm_status upload(Plan* P, T** dst, const std::vector<T>& h, hipStream_t s) {
+  return upload(P, dst, h.data(), h.size(), s);
 }
 
 // Temporary device buffer freed at scope exit.
@@ -1040,14 +1045,10 @@ mm_status build_plan_fixed(const mm_geometry* g, hipStream_t s, Plan** out) {
   int64_t n_coef_total = 0;
   for (int b = 0; b < g->n_bands; ++b)
     n_coef_total = std::max<int64_t>(n_coef_total, g->band_offset[b] + g->band_ncoef[b]);
-  {
-    std::vector<float> coef(g->band_coef, g->band_coef + n_coef_total);
-    std::vector<int64_t> off(g->band_offset, g->band_offset + g->n_bands);
-    std::vector<int32_t> nc(g->band_ncoef, g->band_ncoef + g->n_bands);
-    MM_TRY(upload(P, &P->band_coef, coef, s));
-    MM_TRY(upload(P, &P->band_off, off, s));
-    MM_TRY(upload(P, &P->band_ncoef, nc, s));
-  }
+  // straight from the caller's tables (validated above)
+  MM_TRY(upload(P, &P->band_coef, g->band_coef, static_cast<size_t>(n_coef_total), s));
+  MM_TRY(upload(P, &P->band_off, g->band_offset, static_cast<size_t>(g->n_bands), s));
+  MM_TRY(upload(P, &P->band_ncoef, g->band_ncoef, static_cast<size_t>(g->n_bands), s));
 
   // ---- pointing copies + global accumulation -------------------------------------------------
   MM_TRY(dalloc(P, &P->lpix, n));

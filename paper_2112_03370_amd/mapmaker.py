@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import typing
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -196,6 +197,15 @@ def _host(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
+class BandTable(typing.NamedTuple):
+    """Band coefficients in the ABI's layout: band b is coef[offset[b] : offset[b] + ncoef[b]]
+    (c_0 .. c_lambda).  Accepted wherever a list of per-band arrays is, without the per-plan
+    concatenation."""
+    ncoef: np.ndarray   # int32 [n_bands]
+    offset: np.ndarray  # int64 [n_bands]
+    coef: np.ndarray    # float32
+
+
 def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
                   det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0, flags=0,
                   precision=PRECISION_MIXED, n_poly=0, base_start=None, base_len=None):
@@ -212,13 +222,28 @@ def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands
     bs = _host(blk_start, np.int64)
     bl = _host(blk_len, np.int64)
     bb = _host(blk_band, np.int32)
-    ncoef = np.array([len(b) for b in bands], np.int32)
-    off = np.zeros(len(bands), np.int64)
-    if len(bands) > 1:
-        off[1:] = np.cumsum(ncoef[:-1])
-    coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
-            else np.zeros(1, np.float32))
-    coef = np.ascontiguousarray(coef, np.float32)
+    if isinstance(bands, BandTable):
+        # the table already in the ABI's layout
+        ncoef, off, coef = bands.ncoef, bands.offset, bands.coef
+        ncoef = np.ascontiguousarray(ncoef, np.int32)
+        off = np.ascontiguousarray(off, np.int64)
+        coef = np.ascontiguousarray(coef, np.float32)
+        if ncoef.ndim != 1 or off.shape != ncoef.shape or coef.ndim != 1:
+            raise ValueError("band table: ncoef and offset of one length, coef one-dimensional")
+        if ncoef.size and int((off + ncoef).max()) > coef.size:
+            raise ValueError("band table: offset + ncoef beyond coef")
+        if coef.size == 0:
+            coef = np.zeros(1, np.float32)
+        n_bands = int(ncoef.size)
+    else:
+        ncoef = np.array([len(b) for b in bands], np.int32)
+        off = np.zeros(len(bands), np.int64)
+        if len(bands) > 1:
+            off[1:] = np.cumsum(ncoef[:-1])
+        coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
+                else np.zeros(1, np.float32))
+        coef = np.ascontiguousarray(coef, np.float32)
+        n_bands = len(bands)
     det = None if det_offset is None else _host(det_offset, np.int64)
     g = Geometry()
     g.n_samples = n
@@ -228,7 +253,7 @@ def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands
     g.blk_start = bs.ctypes.data
     g.blk_len = bl.ctypes.data
     g.blk_band = bb.ctypes.data
-    g.n_bands = len(bands)
+    g.n_bands = n_bands
     g.band_ncoef = ncoef.ctypes.data
     g.band_offset = off.ctypes.data
     g.band_coef = coef.ctypes.data

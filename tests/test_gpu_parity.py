@@ -351,6 +351,28 @@ def test_cached_graphs_evicted_and_recaptured(gpu_lib):
             assert err <= 1e-8, (rep, err)
 
 
+def test_band_table_input_matches_band_list(gpu_lib):
+    # A plan built from the band coefficients already in the ABI's table layout (BandTable)
+    # holds the same operator as one built from the list of per-band arrays.
+    prob, ref = case("ground_mini")
+    torch = _torch()
+    pix, wq, wu = _dev(prob.pix), _dev(prob.wq), _dev(prob.wu)
+    table = gpu_lib.BandTable(*prob.band_table())
+    p_list = gpu_lib.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                          prob.blk_band, prob.bands, det_offset=prob.det_offset)
+    p_tab = gpu_lib.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                         prob.blk_band, table, det_offset=prob.det_offset)
+    assert p_tab.info == p_list.info
+    x = np.random.default_rng(13).standard_normal((ref.n_kept, 3))
+    y_list = p_list.apply_A(_dev(x)).cpu().numpy()
+    y_tab = p_tab.apply_A(_dev(x)).cpu().numpy()
+    assert float(_rel(y_tab, y_list)) <= 1e-12
+    bad = gpu_lib.BandTable(table.ncoef, table.offset[:-1], table.coef)
+    with pytest.raises(ValueError):
+        gpu_lib.Plan(pix, wq, wu, prob.n_pix_global, prob.blk_start, prob.blk_len,
+                     prob.blk_band, bad, det_offset=prob.det_offset)
+
+
 def test_white_noise_binned_map_in_one_iteration(gpu_lib):
     prob = synth.make_raster(cfg_id=52, n_dets=3, side=16, dwell=4, lam=0, noise="white")
     ref = O.plan_from_problem(prob)
