@@ -613,7 +613,7 @@ def run_plain(args, prob, name, mm, torch, dev, steps, warmup, refine):
         infos.append(info)
         kts.append(kt)
         log(f"[bench] {name} step {k}: {info['iterations']} + {info['inner_iterations']} it, "
-            f"relres {info['relres']:.2e}, FP32-product true {info['true_relres']:.2e}, FP64 true "
+            f"relres {info['relres']:.2e}, true (PCG iterate) {info['true_relres']:.2e}, FP64 true "
             f"{info['true_relres64']:.2e}, solve {info['ms']:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start

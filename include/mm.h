@@ -181,7 +181,10 @@ typedef struct {
   int32_t iterations;     /* PCG iterations (A products inside the loop) */
   int32_t converged;      /* 1 when the stopping test passed */
   double relres;          /* recursive ||r_k|| / ||b|| */
-  double true_relres;     /* ||b - A x_k|| / ||b|| with one more product, FP64 reductions */
+  double true_relres;     /* ||b - A x_k|| / ||b|| of the PCG iterate x_k with one more product,
+                             FP64 reductions: the plan's product, or the FP64 one when an FP64
+                             residual is taken anyway (refine > 0 or check_fp64 on a Toeplitz
+                             FFT plan, whose FP64 product forms b - A x in one pass) */
   double bnorm;           /* ||b||_2 */
   double ms;              /* wall time of the solve (of the column's group when block >= 2) */
   int32_t block;          /* columns solved together with this one (1: alone) */

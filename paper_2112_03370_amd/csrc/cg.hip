@@ -652,7 +652,7 @@ struct DevVec {
 // right-hand side minus the FP64 product, relative to the FP64 right-hand side.
 mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgParams& outer,
                       int32_t max_steps, double bb_solve, hipStream_t s, double* rel64,
-                      int32_t* steps, int32_t* inner_its) {
+                      int32_t* steps, int32_t* inner_its, double* rel_first) {
   const int64_t nu = 3 * P->n_kept;
   const bool one_product = exact_residual_supported(P);
   DevVec<double> b64, dx;
@@ -664,6 +664,7 @@ mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgPara
   }
   *steps = 0;
   *inner_its = 0;
+  *rel_first = 0.0;
   if (!(bb > 0.0)) {
     *rel64 = 0.0;
     return MM_OK;
@@ -679,6 +680,7 @@ mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgPara
       MM_TRY(sub_norm2(W, b64.p, W.q, W.b, nu, &rr, s));  // W.b = r = b - A x
     }
     *rel64 = std::sqrt(rr / bb);
+    if (*steps == 0) *rel_first = *rel64;
     if (*rel64 < outer.tol || *steps >= max_steps) break;
     PcgParams inner = outer;
     inner.use_x0 = false;
@@ -726,24 +728,24 @@ mm_status pcg_solve(Plan* P, Work& W, const float* d, double* x, const mm_solve_
   CgState st{};
   MM_TRY(pcg_iterate(P, W, x, prm, s, &st));
 
-  // True residual with one more product.
-  double true_rr = 0.0;
-  if (st.bb > 0.0) MM_TRY(residual_norm2(P, W, x, &true_rr, s));
-
   // FP64 true residual (Eq. CGresidual) and iterative refinement for mixed-precision plans.
-  double rel64 = -1.0;
-  int32_t steps = 0, inner_its = 0;
   const bool fp64_products = P->precision == MM_PRECISION_FP64 || P->lambda_max == 0;
-  if (opts.refine > 0 && st.bb > 0.0) {
-    if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
-    MM_TRY(refine_fp64(P, W, d, x, prm, opts.refine, st.bb, s, &rel64, &steps, &inner_its));
+  const bool run_refine = st.bb > 0.0 && (opts.refine > 0 || (opts.check_fp64 && !fp64_products));
+  if (run_refine && alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
+  // True residual of the PCG iterate with one more product: the FP64 residual that the check
+  // or refinement forms first when its FP64 product takes the time-domain residual, else the
+  // plan's own product.
+  const bool true_from_fp64 = run_refine && exact_residual_supported(P);
+  double true_rr = 0.0;
+  if (st.bb > 0.0 && !true_from_fp64) MM_TRY(residual_norm2(P, W, x, &true_rr, s));
+  double rel64 = -1.0, rel_first = 0.0;
+  int32_t steps = 0, inner_its = 0;
+  if (run_refine) {
+    MM_TRY(refine_fp64(P, W, d, x, prm, opts.refine > 0 ? opts.refine : 0, st.bb, s, &rel64,
+                       &steps, &inner_its, &rel_first));
+    if (true_from_fp64) true_rr = rel_first * rel_first * st.bb;
   } else if (opts.check_fp64 && st.bb > 0.0) {
-    if (fp64_products) {
-      rel64 = std::sqrt(true_rr / st.bb);  // the products are FP64 already
-    } else {
-      if (alloc_free) return fail(MM_ERR_UNSUPPORTED, "FP64 check or refinement allocates");
-      MM_TRY(refine_fp64(P, W, d, x, prm, 0, st.bb, s, &rel64, &steps, &inner_its));
-    }
+    rel64 = std::sqrt(true_rr / st.bb);  // the products are FP64 already
   } else if (opts.refine > 0 || opts.check_fp64) {
     rel64 = 0.0;  // b = 0
   }

@@ -373,10 +373,10 @@ struct PcgParams {
 mm_status pcg_iterate(Plan* P, Work& W, double* x, const PcgParams& prm, hipStream_t s,
                       CgState* out);
 // FP64 true residual and iterative refinement after a solve (cg.hip); bb_solve = ||b||^2 of
-// the solve's right-hand side.
+// the solve's right-hand side; *rel_first = the FP64 relative residual of the incoming x.
 mm_status refine_fp64(Plan* P, Work& W, const float* d, double* x, const PcgParams& outer,
                       int32_t max_steps, double bb_solve, hipStream_t s, double* rel64,
-                      int32_t* steps, int32_t* inner_its);
+                      int32_t* steps, int32_t* inner_its, double* rel_first);
 // ||W.b - A x||^2 with the plan's product (uses W.q and the partials).  Synchronous.
 mm_status residual_norm2(Plan* P, Work& W, const double* x, double* rr, hipStream_t s);
 
