@@ -130,6 +130,13 @@ inline unsigned reduce_grid(int count) {
   return static_cast<unsigned>((count + kRedEntries - 1) / kRedEntries);
 }
 
+// The coefficient table's address, opaque to the optimiser: read inside the row loop (broadcast
+// LDS reads) instead of hoisting up to t x t coefficients into registers across all rows.
+__device__ __forceinline__ const double* row_coefs(const double* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 // X_cols[j] += sum_i Z_i a1[i][j];  R_j -= sum_i W_i a1[i][j];  rr partial of ||R_j||^2
 template <int TM>
 __global__ __launch_bounds__(kThreads) void k_block_update(
@@ -145,28 +152,38 @@ __global__ __launch_bounds__(kThreads) void k_block_update(
   for (int j = 0; j < TM; ++j) rr[j] = 0.0;
   for (int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; r < nu;
        r += static_cast<int64_t>(gridDim.x) * kThreads) {
-    double z[TM], w[TM];
+    {  // X += Z a1 (one row of Z live at a time)
+      double z[TM];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      z[i] = i < tz ? Z[i * nu + r] : 0.0;
-      w[i] = i < tz ? W[i * nu + r] : 0.0;
-    }
+      for (int i = 0; i < TM; ++i) z[i] = i < tz ? Z[i * nu + r] : 0.0;
+      const double* c = row_coefs(sa);
 #pragma unroll
-    for (int j = 0; j < TM; ++j) {
-      if (j < ta) {
-        double dx = 0.0, dr = 0.0;
+      for (int j = 0; j < TM; ++j) {
+        if (j < ta) {
+          double dx = 0.0;
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          if (i < tz) {
-            dx += z[i] * sa[i * ta + j];
-            dr += w[i] * sa[i * ta + j];
-          }
+          for (int i = 0; i < TM; ++i)
+            if (i < tz) dx += z[i] * c[i * ta + j];
+          x[static_cast<int64_t>(cols[j]) * nu + r] += dx;
         }
-        double* xc = x + static_cast<int64_t>(cols[j]) * nu;
-        xc[r] += dx;
-        const double rn = R[j * nu + r] - dr;
-        R[j * nu + r] = rn;
-        rr[j] += rn * rn;
+      }
+    }
+    {  // R -= W a1, with the norms
+      double w[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) w[i] = i < tz ? W[i * nu + r] : 0.0;
+      const double* c = row_coefs(sa);
+#pragma unroll
+      for (int j = 0; j < TM; ++j) {
+        if (j < ta) {
+          double dr = 0.0;
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+            if (i < tz) dr += w[i] * c[i * ta + j];
+          const double rn = R[j * nu + r] - dr;
+          R[j * nu + r] = rn;
+          rr[j] += rn * rn;
+        }
       }
     }
   }
@@ -199,13 +216,14 @@ __global__ __launch_bounds__(kThreads) void k_block_direction(double* __restrict
     double z[TM];
 #pragma unroll
     for (int i = 0; i < TM; ++i) z[i] = i < tz ? Z[i * nu + r] : 0.0;
+    const double* c = row_coefs(sa);
 #pragma unroll
     for (int j = 0; j < TM; ++j) {
       if (j < tn) {
         double s = MR[j * nu + r];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
-          if (i < tz) s -= z[i] * sa[i * tn + j];
+          if (i < tz) s -= z[i] * c[i * tn + j];
         Z[j * nu + r] = s;
       }
     }
