@@ -751,8 +751,9 @@ def main():
                     help="also run a plain device copy of this size (for PMC scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; it would shard "
+              "by whole (detector, interval) blocks with one all-reduce of the pixel vector per "
+              "iteration", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -46,7 +46,7 @@ enum {
   MM_ERR_OOM = -4,           /* device allocation failed */
   MM_ERR_HIP = -5,           /* a HIP runtime call failed */
   MM_ERR_BUDGET = -6,        /* serving: request can never fit the memory budget */
-  MM_ERR_UNSUPPORTED = -7,   /* valid input outside what this build implements */
+  MM_ERR_UNSUPPORTED = -7,   /* valid input outside what the library implements */
   MM_ERR_NOT_FOUND = -8      /* serving: unknown ticket */
 };
 
