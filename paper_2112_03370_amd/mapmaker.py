@@ -206,6 +206,30 @@ class BandTable(typing.NamedTuple):
     coef: np.ndarray    # float32
 
 
+def band_arrays(bands):
+    """(ncoef int32, offset int64, coef float32, n_bands) for the geometry's band table, from a
+    BandTable (checked: ncoef and offset of one length, every band inside coef) or from a list
+    of per-band coefficient arrays (concatenated)."""
+    if isinstance(bands, BandTable):
+        ncoef = np.ascontiguousarray(bands.ncoef, np.int32)
+        off = np.ascontiguousarray(bands.offset, np.int64)
+        coef = np.ascontiguousarray(bands.coef, np.float32)
+        if ncoef.ndim != 1 or off.shape != ncoef.shape or coef.ndim != 1:
+            raise ValueError("band table: ncoef and offset of one length, coef one-dimensional")
+        if ncoef.size and (int(off.min()) < 0 or int((off + ncoef).max()) > coef.size):
+            raise ValueError("band table: a band outside coef")
+        if coef.size == 0:
+            coef = np.zeros(1, np.float32)
+        return ncoef, off, coef, int(ncoef.size)
+    ncoef = np.array([len(b) for b in bands], np.int32)
+    off = np.zeros(len(bands), np.int64)
+    if len(bands) > 1:
+        off[1:] = np.cumsum(ncoef[:-1])
+    coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
+            else np.zeros(1, np.float32))
+    return ncoef, off, np.ascontiguousarray(coef, np.float32), len(bands)
+
+
 def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands,
                   det_offset=None, cond_max=0.0, toeplitz_algo=TOEPLITZ_AUTO, fft_size=0, flags=0,
                   precision=PRECISION_MIXED, n_poly=0, base_start=None, base_len=None):
@@ -222,28 +246,7 @@ def make_geometry(pix, wq, wu, n_pix_global, blk_start, blk_len, blk_band, bands
     bs = _host(blk_start, np.int64)
     bl = _host(blk_len, np.int64)
     bb = _host(blk_band, np.int32)
-    if isinstance(bands, BandTable):
-        # the table already in the ABI's layout
-        ncoef, off, coef = bands.ncoef, bands.offset, bands.coef
-        ncoef = np.ascontiguousarray(ncoef, np.int32)
-        off = np.ascontiguousarray(off, np.int64)
-        coef = np.ascontiguousarray(coef, np.float32)
-        if ncoef.ndim != 1 or off.shape != ncoef.shape or coef.ndim != 1:
-            raise ValueError("band table: ncoef and offset of one length, coef one-dimensional")
-        if ncoef.size and int((off + ncoef).max()) > coef.size:
-            raise ValueError("band table: offset + ncoef beyond coef")
-        if coef.size == 0:
-            coef = np.zeros(1, np.float32)
-        n_bands = int(ncoef.size)
-    else:
-        ncoef = np.array([len(b) for b in bands], np.int32)
-        off = np.zeros(len(bands), np.int64)
-        if len(bands) > 1:
-            off[1:] = np.cumsum(ncoef[:-1])
-        coef = (np.concatenate([np.asarray(b, np.float32) for b in bands]) if len(bands)
-                else np.zeros(1, np.float32))
-        coef = np.ascontiguousarray(coef, np.float32)
-        n_bands = len(bands)
+    ncoef, off, coef, n_bands = band_arrays(bands)
     det = None if det_offset is None else _host(det_offset, np.int64)
     g = Geometry()
     g.n_samples = n
